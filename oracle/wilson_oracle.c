@@ -1,0 +1,505 @@
+/*
+ * wilson_oracle.c -- plain, slow FP64 CPU reference for the Wilson-Dirac
+ * inverter path (dslash, even-odd CG on the normal equations, Chebyshev
+ * sign function).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no code, header, table or helper with
+ * the GPU library.
+ *
+ * The paper (Lattice QCD package GWU-code and QUDA with HIP, LATTICE2019)
+ * names the Wilson-Dirac operator (Table 1, QUDA_DIRAC_WILSON), its D-slash
+ * kernel with SU(3) links (Table 2 and its caption), and the overlap fermion
+ * inverter of GWU-code (Sections 1 and 3), but writes down no formula.  The
+ * definitions below are the standard lattice-QCD ones; each convention choice
+ * is one of the readings listed in the design notes.
+ *
+ * Conventions (complex128, AoS, the canonical layout of the library ABI):
+ *   site s = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2, even = 0.
+ *   U[s][mu][a][b]: U_mu(x), 3x3 row-major.  psi[s][spin][colour].
+ *   Gamma matrices in the DeGrand-Rossi basis (g5 = gx gy gz gt = diag(1,1,-1,-1)).
+ *   Hopping term (one output site x):
+ *     (H psi)(x) = sum_mu  b (1 - g_mu) U_mu(x) psi(x+mu)
+ *                        + b (1 + g_mu) U_mu(x-mu)^dagger psi(x-mu)
+ *   with b = -1 on a hop that crosses the time boundary when the time
+ *   direction is antiperiodic, else +1.  The adjoint H^dagger is the same sum
+ *   with (1 - g_mu) and (1 + g_mu) swapped.
+ *   Wilson operator, kappa normalisation:   D_k = 1 - kappa H
+ *   mass normalisation:  D_m(m0) = (4 + m0) - H/2 = D_k / (2 kappa), kappa = 1/(8 + 2 m0)
+ *   overlap kernel:      H_W = g5 D_m(-rho)
+ *
+ * Spin is applied with full 4x4 matrix products (no half-spinor projection);
+ * colour with full 3x3 products.  OpenMP only splits independent sites.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* ---- lattice geometry -------------------------------------------------- */
+
+typedef struct {
+    int L[4];
+    int antiperiodic_t;
+    long V;
+} lattice;
+
+static lattice make_lattice(const int32_t *L, int32_t antiperiodic_t)
+{
+    lattice g;
+    g.V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = L[mu];
+        g.V *= L[mu];
+    }
+    g.antiperiodic_t = antiperiodic_t;
+    return g;
+}
+
+static void site_coords(const lattice *g, long s, int c[4])
+{
+    for (int mu = 0; mu < 4; ++mu) {
+        c[mu] = (int)(s % g->L[mu]);
+        s /= g->L[mu];
+    }
+}
+
+static long site_index(const lattice *g, const int c[4])
+{
+    return c[0] + (long)g->L[0] * (c[1] + (long)g->L[1] * (c[2] + (long)g->L[2] * c[3]));
+}
+
+static int site_parity(const int c[4]) { return (c[0] + c[1] + c[2] + c[3]) & 1; }
+
+/* neighbour of c one step along +mu (dir = +1) or -mu (dir = -1); *bc is the
+ * boundary factor of that hop */
+static long neighbour(const lattice *g, const int c[4], int mu, int dir, double *bc)
+{
+    int n[4] = {c[0], c[1], c[2], c[3]};
+    n[mu] += dir;
+    *bc = 1.0;
+    if (n[mu] == g->L[mu]) {
+        n[mu] = 0;
+        if (mu == 3 && g->antiperiodic_t) *bc = -1.0;
+    } else if (n[mu] < 0) {
+        n[mu] = g->L[mu] - 1;
+        if (mu == 3 && g->antiperiodic_t) *bc = -1.0;
+    }
+    return site_index(g, n);
+}
+
+/* ---- gamma matrices (DeGrand-Rossi) ------------------------------------ */
+
+static void gamma_matrix(int mu, cplx gm[4][4])
+{
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) gm[i][j] = 0;
+    switch (mu) {
+    case 0: /* gamma_x */
+        gm[0][3] = I; gm[1][2] = I; gm[2][1] = -I; gm[3][0] = -I;
+        break;
+    case 1: /* gamma_y */
+        gm[0][3] = -1; gm[1][2] = 1; gm[2][1] = 1; gm[3][0] = -1;
+        break;
+    case 2: /* gamma_z */
+        gm[0][2] = I; gm[1][3] = -I; gm[2][0] = -I; gm[3][1] = I;
+        break;
+    case 3: /* gamma_t */
+        gm[0][2] = 1; gm[1][3] = 1; gm[2][0] = 1; gm[3][1] = 1;
+        break;
+    case 4: /* gamma_5 = gx gy gz gt */
+        gm[0][0] = 1; gm[1][1] = 1; gm[2][2] = -1; gm[3][3] = -1;
+        break;
+    }
+}
+
+void or_gamma(int32_t mu, double *out /* 4x4 complex, row-major */)
+{
+    cplx gm[4][4];
+    gamma_matrix(mu, gm);
+    memcpy(out, gm, sizeof(gm));
+}
+
+/* ---- the hopping term --------------------------------------------------- */
+
+/* acc += b * P * (W psi_y), where W is U (adj = 0) or U^dagger (adj = 1) and
+ * P is the 4x4 spin matrix 1 + sgn*gamma_mu */
+static void accumulate_hop(cplx acc[4][3], const cplx *Umat, int adj, const cplx *psi_y,
+                           cplx gm[4][4], double sgn, double b)
+{
+    cplx chi[4][3];
+    for (int sp = 0; sp < 4; ++sp)
+        for (int a = 0; a < 3; ++a) {
+            cplx v = 0;
+            for (int bb = 0; bb < 3; ++bb) {
+                cplx u = adj ? conj(Umat[bb * 3 + a]) : Umat[a * 3 + bb];
+                v += u * psi_y[sp * 3 + bb];
+            }
+            chi[sp][a] = v;
+        }
+    for (int i = 0; i < 4; ++i)
+        for (int a = 0; a < 3; ++a) {
+            cplx v = 0;
+            for (int j = 0; j < 4; ++j) {
+                cplx pij = (i == j ? 1.0 : 0.0) + sgn * gm[i][j];
+                v += pij * chi[j][a];
+            }
+            acc[i][a] += b * v;
+        }
+}
+
+/* out = H in (dagger = 0) or H^dagger in (dagger = 1) at the output sites of
+ * the given parity (0 even, 1 odd, -1 all); other output sites are set to 0.
+ * With out_parity = p the result reads only the opposite-parity sites of in,
+ * which is the single-parity hop D_{p,1-p}.  in and out hold nrhs fields. */
+void or_hop(const int32_t *L, int32_t antiperiodic_t, const double *U_, const double *in_,
+            double *out_, int32_t nrhs, int32_t out_parity, int32_t dagger)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    const cplx *U = (const cplx *)U_;
+    cplx gms[4][4][4];
+    for (int mu = 0; mu < 4; ++mu) gamma_matrix(mu, gms[mu]);
+    /* forward hop carries 1 - g_mu, backward 1 + g_mu; the adjoint swaps them */
+    const double sfwd = dagger ? +1.0 : -1.0;
+    const double sbwd = -sfwd;
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *in = (const cplx *)in_ + (size_t)r * g.V * 12;
+        cplx *out = (cplx *)out_ + (size_t)r * g.V * 12;
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < g.V; ++s) {
+            int c[4];
+            site_coords(&g, s, c);
+            cplx acc[4][3] = {{0}};
+            if (out_parity < 0 || site_parity(c) == out_parity) {
+                for (int mu = 0; mu < 4; ++mu) {
+                    double b;
+                    long yf = neighbour(&g, c, mu, +1, &b);
+                    accumulate_hop(acc, U + (s * 4 + mu) * 9, 0, in + yf * 12, gms[mu], sfwd, b);
+                    long yb = neighbour(&g, c, mu, -1, &b);
+                    accumulate_hop(acc, U + (yb * 4 + mu) * 9, 1, in + yb * 12, gms[mu], sbwd, b);
+                }
+            }
+            for (int i = 0; i < 4; ++i)
+                for (int a = 0; a < 3; ++a) out[s * 12 + i * 3 + a] = acc[i][a];
+        }
+    }
+}
+
+/* ---- small vector helpers (n complex numbers) -------------------------- */
+
+/* reductions run serially, in index order, so that results do not depend on
+ * the thread count */
+static double vnorm2(const cplx *a, long n)
+{
+    double s = 0;
+    for (long i = 0; i < n; ++i) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return s;
+}
+
+static cplx vdot(const cplx *a, const cplx *b, long n) /* sum conj(a) b */
+{
+    double re = 0, im = 0;
+    for (long i = 0; i < n; ++i) {
+        cplx p = conj(a[i]) * b[i];
+        re += creal(p);
+        im += cimag(p);
+    }
+    return re + I * im;
+}
+
+/* y = a*x + b*y */
+static void vaxpby(cplx a, const cplx *x, cplx b, cplx *y, long n)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) y[i] = a * x[i] + b * y[i];
+}
+
+static void vgamma5(const cplx *in, cplx *out, long V) /* may alias */
+{
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; ++s)
+        for (int sp = 0; sp < 4; ++sp)
+            for (int a = 0; a < 3; ++a) {
+                double g5 = sp < 2 ? 1.0 : -1.0;
+                out[s * 12 + sp * 3 + a] = g5 * in[s * 12 + sp * 3 + a];
+            }
+}
+
+/* zero the sites of the given parity */
+static void vzero_parity(const lattice *g, cplx *v, int parity)
+{
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g->V; ++s) {
+        int c[4];
+        site_coords(g, s, c);
+        if (site_parity(c) == parity)
+            for (int k = 0; k < 12; ++k) v[s * 12 + k] = 0;
+    }
+}
+
+/* ---- full operators ----------------------------------------------------- */
+
+/* out = D_k in = in - kappa H in (dagger: in - kappa H^dagger in), whole lattice */
+void or_wilson(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
+               double *out_, int32_t nrhs, double kappa, int32_t dagger)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    or_hop(L, antiperiodic_t, U, in_, out_, nrhs, -1, dagger);
+    long n = g.V * 12 * (long)nrhs;
+    vaxpby(1.0, (const cplx *)in_, -kappa, (cplx *)out_, n);
+}
+
+/* out = H_W in = g5 ((4 + m0) in - H in / 2), m0 = -rho, whole lattice */
+void or_overlap_kernel(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
+                       double *out_, int32_t nrhs, double rho)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    or_hop(L, antiperiodic_t, U, in_, out_, nrhs, -1, 0);
+    long n = g.V * 12 * (long)nrhs;
+    vaxpby(4.0 - rho, (const cplx *)in_, -0.5, (cplx *)out_, n);
+    vgamma5((const cplx *)out_, (cplx *)out_, g.V * nrhs);
+}
+
+/* ---- even-odd Schur operator ------------------------------------------- */
+/* Vectors live on the whole lattice with zeros on the odd sites.
+ *   D_eo = P_e H P_o,  D_oe = P_o H P_e,  M = 1 - kappa^2 D_eo D_oe   (even sites)
+ *   M^dagger = 1 - kappa^2 D_oe^dagger D_eo^dagger, where D_oe^dagger = P_e H^dagger P_o */
+
+typedef struct {
+    const int32_t *L;
+    int32_t tap;
+    const double *U;
+    double kappa;
+    cplx *tmp; /* one whole-lattice field */
+} schur_op;
+
+static void schur_apply(const schur_op *op, const cplx *in, cplx *out, int dagger, long V)
+{
+    or_hop(op->L, op->tap, op->U, (const double *)in, (double *)op->tmp, 1, 1, dagger);
+    or_hop(op->L, op->tap, op->U, (const double *)op->tmp, (double *)out, 1, 0, dagger);
+    vaxpby(1.0, in, -op->kappa * op->kappa, out, V * 12);
+}
+
+/* Even-odd CG on the normal equations (CGNR) for D_k psi = eta.
+ *   b' = eta_e + kappa D_eo eta_o;  solve M x = b' through M^dagger M x = M^dagger b',
+ *   tracking the residual rt = b' - M x of the original system, which CGNR
+ *   updates for free from q = M p.  Stop when |rt| <= tol |eta| holds for the
+ *   recomputed rt = b' - M x.  Then psi_e = x, psi_o = eta_o + kappa D_oe psi_e.
+ * x holds the initial guess on entry (its odd sites are ignored) and the whole-
+ * lattice solution on exit.  Returns 0 when converged, 1 otherwise.
+ * iters_out: iterations taken; resid_out: |eta - D_k psi| / |eta| with the
+ * whole-lattice operator.  nrhs systems are solved one after the other;
+ * iters_out and resid_out have nrhs entries. */
+int32_t or_cg_eo(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *eta_,
+                 double *x_, int32_t nrhs, double kappa, double tol, int32_t maxiter,
+                 int32_t *iters_out, double *resid_out)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long V = g.V, n = V * 12;
+    cplx *bp = malloc(sizeof(cplx) * n), *rt = malloc(sizeof(cplx) * n);
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *q = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
+    int32_t status = 0;
+    schur_op op = {L, antiperiodic_t, U, kappa, tmp};
+
+    for (int rh = 0; rh < nrhs; ++rh) {
+        const cplx *eta = (const cplx *)eta_ + (size_t)rh * n;
+        cplx *x = (cplx *)x_ + (size_t)rh * n;
+        double eta_norm = sqrt(vnorm2(eta, n));
+        int it = 0, converged = 0;
+
+        /* b' = eta_e + kappa D_eo eta_o */
+        or_hop(L, antiperiodic_t, U, (const double *)eta, (double *)bp, 1, 0, 0);
+        vaxpby(1.0, eta, kappa, bp, n);
+        vzero_parity(&g, bp, 1);
+        vzero_parity(&g, x, 1);
+
+        if (eta_norm == 0.0) {
+            memset(x, 0, sizeof(cplx) * n);
+            iters_out[rh] = 0;
+            resid_out[rh] = 0.0;
+            continue;
+        }
+        /* rt = b' - M x;  r = M^dagger rt;  p = r;  gamma = |r|^2 */
+        schur_apply(&op, x, q, 0, V);
+        memcpy(rt, bp, sizeof(cplx) * n);
+        vaxpby(-1.0, q, 1.0, rt, n);
+        schur_apply(&op, rt, r, 1, V);
+        memcpy(p, r, sizeof(cplx) * n);
+        double gam = vnorm2(r, n);
+
+        while (it < maxiter) {
+            if (sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+                /* confirm on the recomputed residual */
+                schur_apply(&op, x, q, 0, V);
+                memcpy(rt, bp, sizeof(cplx) * n);
+                vaxpby(-1.0, q, 1.0, rt, n);
+                if (sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+                    converged = 1;
+                    break;
+                }
+                schur_apply(&op, rt, r, 1, V);
+                gam = vnorm2(r, n);
+                memcpy(p, r, sizeof(cplx) * n);
+            }
+            schur_apply(&op, p, q, 0, V); /* q = M p */
+            double alpha = gam / vnorm2(q, n);
+            vaxpby(alpha, p, 1.0, x, n);   /* x += alpha p */
+            vaxpby(-alpha, q, 1.0, rt, n); /* rt -= alpha q */
+            schur_apply(&op, rt, r, 1, V); /* s = M^dagger rt */
+            double gam_new = vnorm2(r, n);
+            vaxpby(1.0, r, gam_new / gam, p, n); /* p = s + beta p */
+            gam = gam_new;
+            ++it;
+        }
+        if (!converged && sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+            schur_apply(&op, x, q, 0, V);
+            memcpy(rt, bp, sizeof(cplx) * n);
+            vaxpby(-1.0, q, 1.0, rt, n);
+            converged = sqrt(vnorm2(rt, n)) <= tol * eta_norm;
+        }
+
+        /* psi_o = eta_o + kappa D_oe psi_e */
+        or_hop(L, antiperiodic_t, U, (const double *)x, (double *)tmp, 1, 1, 0);
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < V; ++s) {
+            int c[4];
+            site_coords(&g, s, c);
+            if (site_parity(c) == 1)
+                for (int k = 0; k < 12; ++k) x[s * 12 + k] = eta[s * 12 + k] + kappa * tmp[s * 12 + k];
+        }
+
+        /* independent true residual with the whole-lattice operator */
+        or_wilson(L, antiperiodic_t, U, (const double *)x, (double *)tmp, 1, kappa, 0);
+        vaxpby(1.0, eta, -1.0, tmp, n);
+        iters_out[rh] = it;
+        resid_out[rh] = sqrt(vnorm2(tmp, n)) / eta_norm;
+        if (!converged) status = 1;
+    }
+    free(bp); free(rt); free(r); free(p); free(q); free(tmp);
+    return status;
+}
+
+/* ---- Chebyshev approximation of the sign function ----------------------- */
+
+/* Coefficients of the Chebyshev interpolant of f(x) = x^{-1/2} on [lo, hi],
+ * degree d (N = d + 1 terms), at the N first-kind Chebyshev nodes:
+ *   theta_k = pi (k + 1/2) / N,  x_k = (hi - lo)/2 cos theta_k + (hi + lo)/2
+ *   c_j = (2/N) sum_k f(x_k) cos(j theta_k),  p(x) = c_0/2 + sum_{j>=1} c_j T_j(y(x))
+ * with y(x) = (2x - hi - lo) / (hi - lo). */
+void or_cheb_coeffs(int32_t degree, double lo, double hi, double *c)
+{
+    int N = degree + 1;
+    for (int j = 0; j < N; ++j) {
+        double s = 0;
+        for (int k = 0; k < N; ++k) {
+            double th = M_PI * (k + 0.5) / N;
+            double xk = 0.5 * (hi - lo) * cos(th) + 0.5 * (hi + lo);
+            s += cos(j * th) / sqrt(xk);
+        }
+        c[j] = 2.0 * s / N;
+    }
+}
+
+/* Scalar evaluation of that polynomial at x, by the same Clenshaw recurrence. */
+double or_cheb_eval(int32_t degree, const double *c, double lo, double hi, double x)
+{
+    double y = (2.0 * x - hi - lo) / (hi - lo);
+    double b1 = 0, b2 = 0;
+    for (int j = degree; j >= 1; --j) {
+        double b0 = 2.0 * y * b1 - b2 + c[j];
+        b2 = b1;
+        b1 = b0;
+    }
+    return y * b1 - b2 + 0.5 * c[0];
+}
+
+/* out = eps(H_W) in ~= s^{-1/2} H_W p(H_W^2 / s) in, whole lattice, nrhs fields.
+ * p is the degree-d Chebyshev interpolant of x^{-1/2} on [lo, hi]; it is
+ * applied by the Clenshaw recurrence with Y = (2 H_W^2 / s - hi - lo)/(hi - lo):
+ *   b_{N} = b_{N+1} = 0,  b_j = 2 Y b_{j+1} - b_{j+2} + c_j v  (j = N-1 .. 1),
+ *   p v = Y b_1 - b_2 + c_0 v / 2. */
+void or_sign_cheb(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
+                  double *out_, int32_t nrhs, double rho, int32_t degree, double lo, double hi,
+                  double scale)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    int N = degree + 1;
+    double *c = malloc(sizeof(double) * N);
+    or_cheb_coeffs(degree, lo, hi, c);
+    cplx *b0 = malloc(sizeof(cplx) * n), *b1 = malloc(sizeof(cplx) * n);
+    cplx *b2 = malloc(sizeof(cplx) * n), *w = malloc(sizeof(cplx) * n);
+    cplx *yb = malloc(sizeof(cplx) * n);
+    const double ay = 2.0 / ((hi - lo) * scale), by = -(hi + lo) / (hi - lo);
+
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *v = (const cplx *)in_ + (size_t)r * n;
+        cplx *out = (cplx *)out_ + (size_t)r * n;
+        memset(b1, 0, sizeof(cplx) * n); /* b_{j+1} */
+        memset(b2, 0, sizeof(cplx) * n); /* b_{j+2} */
+        for (int j = N - 1; j >= 1; --j) {
+            /* yb = Y b1 = ay H_W (H_W b1) + by b1 */
+            or_overlap_kernel(L, antiperiodic_t, U, (const double *)b1, (double *)w, 1, rho);
+            or_overlap_kernel(L, antiperiodic_t, U, (const double *)w, (double *)yb, 1, rho);
+            vaxpby(by, b1, ay, yb, n);
+            /* b0 = 2 yb - b2 + c_j v */
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) b0[i] = 2.0 * yb[i] - b2[i] + c[j] * v[i];
+            cplx *t = b2;
+            b2 = b1;
+            b1 = b0;
+            b0 = t;
+        }
+        /* p v = Y b1 - b2 + c_0 v / 2 */
+        or_overlap_kernel(L, antiperiodic_t, U, (const double *)b1, (double *)w, 1, rho);
+        or_overlap_kernel(L, antiperiodic_t, U, (const double *)w, (double *)yb, 1, rho);
+        vaxpby(by, b1, ay, yb, n);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) w[i] = yb[i] - b2[i] + 0.5 * c[0] * v[i];
+        /* out = s^{-1/2} H_W (p v) */
+        or_overlap_kernel(L, antiperiodic_t, U, (const double *)w, (double *)out, 1, rho);
+        vaxpby(0.0, out, 1.0 / sqrt(scale), out, n);
+    }
+    free(c); free(b0); free(b1); free(b2); free(w); free(yb);
+}
+
+/* Largest eigenvalue of H_W^2 by power iteration from the start vector v0
+ * (Rayleigh quotient after iters steps). */
+double or_hw2_lmax(const int32_t *L, int32_t antiperiodic_t, const double *U, double rho,
+                   const double *v0, int32_t iters)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    cplx *v = malloc(sizeof(cplx) * n), *w = malloc(sizeof(cplx) * n), *u = malloc(sizeof(cplx) * n);
+    memcpy(v, v0, sizeof(cplx) * n);
+    double lam = 0;
+    double nv = sqrt(vnorm2(v, n));
+    vaxpby(0.0, v, 1.0 / nv, v, n);
+    for (int it = 0; it < iters; ++it) {
+        or_overlap_kernel(L, antiperiodic_t, U, (const double *)v, (double *)u, 1, rho);
+        or_overlap_kernel(L, antiperiodic_t, U, (const double *)u, (double *)w, 1, rho);
+        lam = creal(vdot(v, w, n));
+        double nw = sqrt(vnorm2(w, n));
+        for (long i = 0; i < n; ++i) v[i] = w[i] / nw;
+    }
+    free(v); free(w); free(u);
+    return lam;
+}
+
+/* Number of OpenMP threads the oracle runs on. */
+int32_t or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

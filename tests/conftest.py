@@ -1,0 +1,20 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: larger CPU-only case")
+
+
+def pytest_runtest_setup(item):
+    # print the case name before any GPU work so that a crash names it
+    if item.get_closest_marker("gpu") is not None:
+        sys.stdout.write("\n[gpu-case] %s\n" % item.nodeid)
+        sys.stdout.flush()
