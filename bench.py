@@ -1,0 +1,216 @@
+"""Benchmark of the Wilson-Dirac inverter hot path on one MI355X.
+
+Workload: 24^3 x 48 lattice, smooth random links U = exp(i 0.3 H) (plaquette
+~0.61), kappa = 0.1245, one Gaussian source, true residual 1e-10.  A step is
+one complete solve of D psi = eta by mixed-precision even-odd CGNR (sloppy
+storage --sloppy, FP32 arithmetic, FP64 reliable updates and reductions):
+source packing, every D-slash and BLAS kernel of the iteration, the FP64
+residual recomputations, the odd-site reconstruction and the FP64 true
+residual.  Inputs are resident in HBM before the timed region.
+
+value  = algorithmic HBM bytes of every kernel of the solve / solve time (GB/s)
+roofline = the dominant kernel (the single-parity hop): algorithmic bytes per
+           launch / mean launch duration from HIP events on its stream, against
+           the 8 TB/s HBM peak
+cpu_baseline = the FP64 CPU oracle's CGNR on the same lattice, a bounded number
+           of iterations, in the same byte model.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sloppy f16]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GB/s & % HBM peak; CG time to 1e-10 resid, mixed/batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cg_iteration_bytes(w, prec, recon, vh):
+    """Algorithmic bytes of one CGNR iteration per the library's byte model:
+    4 hops (+2 epilogue reads), x/r update (6 passes), p = s + beta p (3)."""
+    site = {"f64": 192, "f32": 96, "f16": 52, "bf16": 52}[prec]
+    return vh * (4 * w.wl_hop_bytes_per_site(prec, recon, 1) + 2 * site + 6 * site + 3 * site)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sloppy", default="f16", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--recon", type=int, default=12)
+    ap.add_argument("--delta", type=float, default=0.1)
+    ap.add_argument("--lattice", default="24,24,24,48")
+    ap.add_argument("--cpu-iters", type=int, default=12, help="oracle CG iterations timed for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP64 / D-slash side measurements")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import lattice_inputs as li
+    from paper_2001_05706_amd import wilson as w
+
+    w.lib()
+    dev = torch.device("cuda:0")
+    L = tuple(int(v) for v in a.lattice.split(","))
+    V = L[0] * L[1] * L[2] * L[3]
+    vh = V // 2
+    kappa, tol, maxiter = 0.1245, 1e-10, 5000
+
+    t0 = time.time()
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2002)
+    log("inputs generated in %.1f s" % (time.time() - t0))
+    Ud = torch.from_numpy(U.view(np.float64)).to(dev)
+    etad = torch.from_numpy(eta.view(np.float64)).to(dev)
+    x = torch.zeros_like(etad)
+    g = w.Gauge(L, Ud)
+    stream = torch.cuda.current_stream()
+
+    def solve(sloppy, recon):
+        x.zero_()
+        st, info = w.wilson_cg(g, etad, x, 1, kappa, tol, maxiter, sloppy, recon, a.delta, stream=stream)
+        return info[0]
+
+    for i in range(a.warmup):
+        info = solve(a.sloppy, a.recon)
+        log("warmup %d: %d iters, %d updates, true resid %.2e, %.2f ms" %
+            (i, info["iters"], info["reliable_updates"], info["true_resid"], info["seconds"] * 1e3))
+
+    # ---- timed region: K complete solves, graphs on, nothing else on the stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [solve(a.sloppy, a.recon) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    gbytes = sum(i["gbytes"] for i in infos)
+    value = gbytes / (t1 - t0)
+    worst = max(i["true_resid"] for i in infos)
+    log("timed: %d solves, %.3f ms/solve, %.1f GB/s algorithmic, worst true resid %.2e" %
+        (a.steps, ms_per_step, value, worst))
+    assert all(i["converged"] for i in infos) and worst <= tol
+
+    # ---- per-kernel timing of the dominant kernel over the same K solves:
+    # HIP events bracket every hop launch on its stream (graph replay off)
+    w.wl_prof_enable(True)
+    w.wl_prof_read()
+    for _ in range(a.steps):
+        solve(a.sloppy, a.recon)
+    torch.cuda.synchronize()
+    n_hop, hop_ms, hop_gb = w.wl_prof_read()
+    w.wl_prof_enable(False)
+    hop_avg_us = hop_ms * 1e3 / max(n_hop, 1)
+    achieved = hop_gb / (hop_ms * 1e-3) if hop_ms > 0 else 0.0
+    log("hop launches %d, mean %.2f us, %.1f GB/s" % (n_hop, hop_avg_us, achieved))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "e/o CGNR solve to 1e-10 true residual, %dx%dx%dx%d, eps=0.3 links, kappa=%g, 1 Gaussian rhs"
+                        % (L + (kappa,)),
+            "lattice": list(L),
+            "sloppy_storage": a.sloppy,
+            "recon": a.recon,
+            "arithmetic": "f32 sloppy, f64 reliable updates / reductions / true residual",
+            "delta": a.delta,
+            "iters": infos[0]["iters"],
+            "reliable_updates": infos[0]["reliable_updates"],
+            "true_resid": worst,
+        },
+        "roofline": {
+            "kernel": "k_hop (single-parity Wilson hop, %s recon-%d, fused epilogue)" % (a.sloppy, a.recon),
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "mean_launch_us": round(hop_avg_us, 3),
+            "launches": n_hop,
+        },
+    }
+
+    if not a.no_extra:
+        # plain FP64 GPU solver (recon 18) and other sloppy precisions, same workload
+        cmp = {}
+        for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]:
+            solve(sl, rc)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                tt = time.perf_counter()
+                inf = solve(sl, rc)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - tt)
+            cmp[sl] = {"ms": round(min(ts) * 1e3, 3), "iters": inf["iters"], "updates": inf["reliable_updates"],
+                       "true_resid": inf["true_resid"]}
+            log("solve %s: %.2f ms, %d iters, resid %.2e" % (sl, min(ts) * 1e3, inf["iters"], inf["true_resid"]))
+        out["cg_time_to_1e-10_ms"] = cmp
+        out["cg_speedup_vs_fp64"] = round(cmp["f64"]["ms"] / cmp[a.sloppy]["ms"], 3)
+        # stand-alone D-slash (hop only), warm and cold operand protocols
+        ds = {}
+        for prec, rc in [("f64", 18), ("f32", 12), ("f16", 12)]:
+            bps = w.wl_hop_bytes_per_site(prec, rc, 1)
+            for nsets, name in [(1, "warm"), (4, "cold")]:
+                sec = w.wl_bench_dslash(g, prec, rc, 1, 0, nsets, 100, stream)
+                gbs = bps * vh / sec / 1e9
+                ds["%s_r%d_%s" % (prec, rc, name)] = {"us": round(sec * 1e6, 2), "GBs": round(gbs, 1),
+                                                     "TFLOPs": round(1320 * vh / sec / 1e12, 3)}
+                log("dslash %s r%d %s: %.2f us, %.1f GB/s" % (prec, rc, name, sec * 1e6, gbs))
+        out["dslash"] = ds
+        sec = w.wl_bench_copy(1 << 30, 20, stream)
+        out["copy_GBs"] = round(2 * (1 << 30) / sec / 1e9, 1)
+        log("copy 1 GiB: %.1f GB/s (read + write)" % out["copy_GBs"])
+
+    if not a.no_cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        _, _, it, _ = oracle.cg_eo(L, U, eta, kappa, tol, maxiter=a.cpu_iters)
+        dt = time.perf_counter() - t0
+        cpu_bytes = a.cpu_iters * cg_iteration_bytes(w, "f64", 18, vh)
+        out["cpu_baseline"] = {
+            "value": round(cpu_bytes / dt / 1e9, 3),
+            "unit": "GB/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle e/o CGNR on the same %dx%dx%dx%d system, %d iterations (%.1f s incl. setup), "
+                      "FP64 recon-18 byte model" % (L + (a.cpu_iters, dt)),
+            "ms_per_iteration": round(dt * 1e3 / a.cpu_iters, 1),
+        }
+        log("cpu oracle: %.1f s for %d iterations" % (dt, a.cpu_iters))
+
+    g.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

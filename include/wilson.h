@@ -1,0 +1,195 @@
+/*
+ * wilson.h -- C ABI of the MI355X (gfx950) Wilson-Dirac inverter library.
+ *
+ * The library applies the Wilson-Dirac D-slash (the kernel Table 2 of the paper
+ * measures, with SU(3) links compressed to 12 reals as its caption states),
+ * solves the Wilson system with even-odd preconditioned CG on the normal
+ * equations in mixed precision (QUDA_DIRAC_WILSON, Table 1; mixed-precision
+ * inverters of the QUDA line of work cited in Section 1), solves batches of
+ * systems in one launch sequence, and applies the Chebyshev-polynomial sign
+ * function of the Wilson kernel used by GWU-code's overlap inverter
+ * (Sections 1 and 3).  The paper prints no formula; the definitions below are
+ * the textbook ones.
+ *
+ * Canonical layouts (the only layouts a caller sees).  Complex numbers are
+ * interleaved (re, im) doubles.
+ *   lattice   L = (Lx, Ly, Lz, Lt), every L even and >= 2;
+ *             site s = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2, even = 0
+ *   links     U[s][mu][a][b]      3x3 row-major, mu = 0..3 = x, y, z, t;
+ *             U_mu(x) transports the field at x+mu to x; every U must be SU(3)
+ *             for the 12-real compression (recon = 12) to be exact
+ *   spinors   psi[r][s][spin][col] DeGrand-Rossi gamma basis, r = RHS index
+ *
+ * Operators:
+ *   (H psi)(x) = sum_mu b (1 - g_mu) U_mu(x) psi(x+mu) + b (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)
+ *   b = -1 on hops across the time boundary when t is antiperiodic, else +1;
+ *   H^+ swaps (1 - g_mu) and (1 + g_mu).  D = 1 - kappa H (kappa normalisation).
+ *   Overlap kernel H_W = g5 ((4 + m0) - H/2) with m0 = -rho.
+ *
+ * Ownership and memory: every field pointer is a DEVICE pointer (hipMalloc'd
+ * or torch-allocated) owned by the caller; the library never frees it.  The
+ * library owns a wl_gauge (packed copies of the links in each precision and
+ * compression asked for so far, built lazily) and its internal workspaces.
+ * Handles are not thread-safe: one host thread per handle at a time.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * All device work of a call is enqueued on it.  wilson_dslash returns without
+ * synchronising; solver and sign-function calls synchronise the stream before
+ * they return because they fill host-side results.
+ *
+ * Errors: every entry point returns a wl_status and never aborts or throws.
+ * Arguments are validated before any device work; wl_last_error() returns a
+ * thread-local description of the most recent failure.  A pointer that
+ * hipPointerGetAttributes does not report as device memory is WL_ERR_ARG.
+ */
+#ifndef WILSON_MI355X_H
+#define WILSON_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WL_OK = 0,
+    WL_ERR_ARG = 1,       /* null / non-device pointer, bad scalar argument */
+    WL_ERR_GEOM = 2,      /* lattice dims not all even and >= 2, or too large */
+    WL_ERR_PREC = 3,      /* unsupported precision / compression combination */
+    WL_ERR_NOMEM = 4,     /* device allocation failed */
+    WL_ERR_HIP = 5,       /* a HIP runtime call failed */
+    WL_ERR_NOCONV = 6,    /* solver reached maxiter; x holds the last iterate */
+    WL_ERR_NONFINITE = 7  /* NaN or Inf met in a reduction or an input */
+} wl_status;
+
+/* Storage precision of fields.  Arithmetic is FP64 for WL_F64 and FP32
+ * otherwise; WL_F16 / WL_BF16 spinors carry one FP32 norm per site
+ * (stored value = v / max|v| over the site's 24 reals). */
+typedef enum { WL_F64 = 0, WL_F32 = 1, WL_F16 = 2, WL_BF16 = 3 } wl_prec;
+
+typedef struct {
+    int32_t L[4];            /* Lx, Ly, Lz, Lt: each even, >= 2 */
+    int32_t antiperiodic_t;  /* 1: antiperiodic in time, 0: periodic */
+} wl_geom;
+
+typedef struct {
+    int32_t iters;                 /* sloppy CG iterations */
+    int32_t reliable_updates;      /* FP64 residual recomputations */
+    int32_t converged;             /* 1 if true_resid <= tol */
+    int32_t precision_escalations; /* sloppy precision raised after stagnation */
+    double true_resid;             /* |eta - D psi| / |eta|, FP64, whole-lattice operator */
+    double seconds;                /* wall time of the solve (host clock) */
+    double gbytes;                 /* algorithmic HBM bytes of all kernels launched, 1e9 B */
+} wl_solve_info;
+
+typedef struct wl_gauge_s *wl_gauge;
+
+/* ---------------------------------------------------------------- gauge */
+
+/* Build a gauge handle from canonical FP64 links U_dev (device pointer,
+ * 4 * V * 9 complex doubles).  The links are copied; U_dev may be freed after
+ * the call returns.  Packed copies per precision are created lazily on first
+ * use, on the stream of that call. */
+wl_status wl_gauge_create(const wl_geom *geom, const double *U_dev, void *stream, wl_gauge *out);
+
+/* Release a handle and all device memory it owns.  NULL is ignored. */
+void wl_gauge_destroy(wl_gauge U);
+
+/* ---------------------------------------------------------------- dslash */
+
+/* The Wilson D-slash of Table 2 on nrhs canonical fields in -> out (device).
+ *   parity 0 / 1: out_p = H_{p,1-p} in_{1-p} -- the single-parity hopping term
+ *                 (1320 flop per output site); out is zero on the other parity
+ *   parity -1   : out = D in = in - kappa H in on the whole lattice
+ * dagger = 1 applies H^+ instead of H.  Arithmetic and storage follow prec
+ * (in and out are converted to and from the packed layout inside the call);
+ * recon = 12 (two rows, third rebuilt) or 18 (full matrix; WL_F64/WL_F32 only).
+ * in and out must not overlap.  Asynchronous on `stream`. */
+wl_status wilson_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double kappa,
+                        int32_t parity, int32_t dagger, wl_prec prec, int32_t recon, void *stream);
+
+/* ---------------------------------------------------------------- solvers */
+
+/* Solve D psi = eta (kappa normalisation) for nrhs right-hand sides by
+ * even-odd preconditioned CG on the normal equations:
+ *   b' = eta_e + kappa D_eo eta_o,  M = 1 - kappa^2 D_eo D_oe,
+ *   CGNR on M^+ M x = M^+ b', psi_e = x, psi_o = eta_o + kappa D_oe psi_e.
+ * Iterations run in the `sloppy` storage precision (FP32 arithmetic unless
+ * WL_F64) with FP64 reliable updates: the solution accumulates in FP64 and the
+ * residual b' - M x is recomputed in FP64 whenever the sloppy residual has
+ * fallen by `delta` (0 < delta < 1; typical 0.1) since the last update.  The
+ * solve stops when the FP64 residual is <= tol * |eta|.
+ * eta, x: device, nrhs canonical fields; x holds the initial guess on entry
+ * (zero it for none) and the solution on exit.  info: host array of nrhs.
+ * A zero source gives x = 0, converged = 1.  On WL_ERR_NOCONV x holds the last
+ * iterate and info is filled.  Synchronises `stream`. */
+wl_status wilson_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double tol,
+                    int32_t maxiter, wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info,
+                    void *stream);
+
+/* Solve nsys independent systems (each its own gauge handle and geometry,
+ * nrhs[i] right-hand sides, kappa[i]) together: every kernel launch of an
+ * iteration covers all still-unconverged right-hand sides of all systems,
+ * using device-resident per-system descriptors, and the iteration chunks are
+ * replayed from a captured HIP graph.  eta[i], x[i]: device pointers as in
+ * wilson_cg.  info: host array of sum(nrhs) entries, system-major.
+ * Synchronises `stream`. */
+wl_status wilson_cg_multi(int32_t nsys, const wl_gauge *U, const double *const *eta, double *const *x,
+                          const int32_t *nrhs, const double *kappa, double tol, int32_t maxiter,
+                          wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------- overlap sign */
+
+/* out = eps(H_W) in ~= scale^{-1/2} H_W p(H_W^2 / scale) in on the whole
+ * lattice, for nrhs canonical fields (device).  p is the Chebyshev interpolant
+ * of degree `degree` of x^{-1/2} on [lo, hi] at the degree+1 first-kind
+ * Chebyshev nodes, applied by the Clenshaw recurrence.  H_W = g5 D_m(-rho)
+ * (mass normalisation, kappa = 1/(8 - 2 rho)).  scale > 0 is the number the
+ * spectrum of H_W^2 is divided by; scale <= 0 asks the library to estimate
+ * 1.02 x lambda_max(H_W^2) by power iteration first.  prec is the storage
+ * precision of the iteration (WL_F64 or WL_F32).  Synchronises `stream`. */
+wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t nrhs, double rho,
+                            int32_t degree, double lo, double hi, double scale, wl_prec prec,
+                            int32_t recon, void *stream);
+
+/* Largest eigenvalue of H_W^2 (m0 = -rho) estimated by `iters` steps of power
+ * iteration from the canonical field v0 (device); FP64.  Synchronises. */
+wl_status wl_hw2_lmax(wl_gauge U, double rho, const double *v0, int32_t iters, double *lmax, void *stream);
+
+/* ---------------------------------------------------------------- errors */
+
+const char *wl_status_string(wl_status s);
+const char *wl_last_error(void);
+
+/* ---------------------------------------------------------------- measurement */
+
+/* Time the single-parity hop kernel on library-owned packed fields (no
+ * conversion inside the timed region): `reps` back-to-back launches on
+ * `stream`, measured with HIP events on that stream.  nsets >= 1 independent
+ * (links, in, out) sets are rotated so that consecutive launches do not find
+ * their operands in the caches (cold protocol) -- nsets = 1 is the warm
+ * protocol of a solver.  Returns the mean seconds per launch. */
+wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs, int32_t parity,
+                          int32_t nsets, int32_t reps, double *seconds_per_call, void *stream);
+
+/* Time a plain device copy of `bytes` bytes (read + write), the measured
+ * bandwidth reference for the roofline; mean seconds per copy. */
+wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, void *stream);
+
+/* Per-kernel timing of the library's own launches: when enabled, every hop
+ * launch is bracketed by HIP events on its stream and its duration added to a
+ * running total.  wl_prof_read returns launches and total milliseconds of hop
+ * launches since the last reset and resets the counters. */
+wl_status wl_prof_enable(int32_t on);
+wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes);
+
+/* Algorithmic bytes per output site of one single-parity hop launch for a
+ * storage precision, compression and RHS count: 8 links shared by the nrhs
+ * right-hand sides, plus one input and one output spinor per RHS. */
+double wl_hop_bytes_per_site(wl_prec prec, int32_t recon, int32_t nrhs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WILSON_MI355X_H */

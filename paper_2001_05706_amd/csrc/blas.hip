@@ -1,0 +1,220 @@
+// blas.hip -- fused BLAS-1 kernels of the solvers with per-vector scalars
+// read from device memory and fused FP64 norm reductions (the vector
+// operations GWU-code ran through Thrust, Section 3, and QUDA's multi-vector
+// BLAS/reduction kernels, Section 2).
+//
+// Products are formed in the storage arithmetic (FP32 for FP32/FP16/BF16,
+// FP64 for FP64); norms accumulate per site in that arithmetic and across
+// sites in FP64 with the deterministic block reduction.
+#include "wl_reduce.h"
+#include "wl_kernels.h"
+
+namespace wl {
+
+#define WL_BLAS_PROLOGUE                                              \
+    const int lb = xcd_remap(blockIdx.x, a.nblocks);                  \
+    const BlkMap bm = a.map[lb];                                      \
+    if (a.active && !a.active[bm.v]) return;                          \
+    const VecDesc vd = a.vec[bm.v];                                   \
+    const SysDesc sd = a.sys[vd.sys];                                 \
+    const int cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;      \
+    const bool live = cb < sd.Vh;
+
+template <int P> __device__ __forceinline__ const void *vbase(const void *f, const VecDesc &vd)
+{
+    return (const typename SpinorFmt<P>::chunk *)f + (size_t)vd.site_off * SpinorFmt<P>::nchunk;
+}
+template <int P> __device__ __forceinline__ void *vbase(void *f, const VecDesc &vd)
+{
+    return (typename SpinorFmt<P>::chunk *)f + (size_t)vd.site_off * SpinorFmt<P>::nchunk;
+}
+__device__ __forceinline__ float *nbase(float *n, const VecDesc &vd) { return n ? n + vd.site_off : nullptr; }
+
+template <int P>
+__global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    double nrm = 0.0;
+    if (live) {
+        const T al = (T)a.s0[bm.v];
+        T x[24], p[24], r[24], q[24];
+        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, p);
+        load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
+        load_spinor<P>(vbase<P>(a.f[3], vd), nbase(a.fn[3], vd), sd.stride, cb, q);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            x[k] += al * p[k];
+            r[k] -= al * q[k];
+        }
+        store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        store_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
+        nrm = site_norm2(r);
+    }
+    if (a.red.kind != RED_NONE) block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_xpay(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    const T be = (T)a.s0[bm.v];
+    T p[24], s[24];
+    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) p[k] = s[k] + be * p[k];
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_accum(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    double y[24];
+    T x[24];
+    load_spinor<P_F64>(vbase<P_F64>(a.f[0], vd), nullptr, sd.stride, cb, y);
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        y[k] += (double)x[k];
+        x[k] = 0;
+    }
+    store_spinor<P_F64>(vbase<P_F64>(a.f[0], vd), nullptr, sd.stride, cb, y);
+    store_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_norm2(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    double nrm = 0.0;
+    if (live) {
+        T x[24];
+        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        nrm = site_norm2(x);
+    }
+    block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_zero(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    T x[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) x[k] = 0;
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_fill(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    T x[24];
+    uint32_t h = (uint32_t)(vd.site_off + cb) * 2654435761u + 12345u;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        h ^= h << 13;
+        h ^= h >> 17;
+        h ^= h << 5;
+        x[k] = (T)((float)(h & 0xFFFFu) * (1.0f / 32768.0f) - 1.0f);
+    }
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_scale_rsqrt(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    const double n2 = a.s0[bm.v];
+    const T f = (T)(n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0);
+    T x[24];
+    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) x[k] *= f;
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+}
+
+template <int PD, int PS>
+__global__ __launch_bounds__(256) void k_convert(BlasArgs a)
+{
+    using TS = typename SpinorFmt<PS>::real;
+    using TD = typename SpinorFmt<PD>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    TS x[24];
+    TD y[24];
+    load_spinor<PS>(vbase<PS>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) y[k] = (TD)x[k];
+    store_spinor<PD>(vbase<PD>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, y);
+}
+
+template <int P>
+static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_t s)
+{
+    dim3 g(a.nblocks), b(block);
+    switch (op) {
+    case BL_CG_UPDATE: hipLaunchKernelGGL(k_cg_update<P>, g, b, 0, s, a); break;
+    case BL_XPAY: hipLaunchKernelGGL(k_xpay<P>, g, b, 0, s, a); break;
+    case BL_ACCUM: hipLaunchKernelGGL(k_accum<P>, g, b, 0, s, a); break;
+    case BL_NORM2: hipLaunchKernelGGL(k_norm2<P>, g, b, 0, s, a); break;
+    case BL_ZERO: hipLaunchKernelGGL(k_zero<P>, g, b, 0, s, a); break;
+    case BL_COPY: hipLaunchKernelGGL((k_convert<P, P>), g, b, 0, s, a); break;
+    case BL_FILL: hipLaunchKernelGGL(k_fill<P>, g, b, 0, s, a); break;
+    case BL_SCALE_RSQRT: hipLaunchKernelGGL(k_scale_rsqrt<P>, g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s)
+{
+    switch (prec) {
+    case P_F64: return launch_blas_t<P_F64>(op, a, block, s);
+    case P_F32: return launch_blas_t<P_F32>(op, a, block, s);
+    case P_F16: return launch_blas_t<P_F16>(op, a, block, s);
+    case P_BF16: return launch_blas_t<P_BF16>(op, a, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int PD>
+static hipError_t launch_convert_d(int ps, const BlasArgs &a, int block, hipStream_t s)
+{
+    dim3 g(a.nblocks), b(block);
+    switch (ps) {
+    case P_F64: hipLaunchKernelGGL((k_convert<PD, P_F64>), g, b, 0, s, a); break;
+    case P_F32: hipLaunchKernelGGL((k_convert<PD, P_F32>), g, b, 0, s, a); break;
+    case P_F16: hipLaunchKernelGGL((k_convert<PD, P_F16>), g, b, 0, s, a); break;
+    case P_BF16: hipLaunchKernelGGL((k_convert<PD, P_BF16>), g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int pd, int ps, const BlasArgs &a, int block, hipStream_t s)
+{
+    switch (pd) {
+    case P_F64: return launch_convert_d<P_F64>(ps, a, block, s);
+    case P_F32: return launch_convert_d<P_F32>(ps, a, block, s);
+    case P_F16: return launch_convert_d<P_F16>(ps, a, block, s);
+    case P_BF16: return launch_convert_d<P_BF16>(ps, a, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wl

@@ -1,0 +1,462 @@
+// cg.hip -- even-odd preconditioned CG on the normal equations (CGNR) for the
+// Wilson operator, mixed precision with FP64 reliable updates, for one set of
+// systems x right-hand sides at once (QUDA_DIRAC_WILSON of Table 1; the
+// mixed-precision inverters of the QUDA line of work cited in Section 1).
+//
+//   b' = eta_e + kappa D_eo eta_o,   M = 1 - kappa^2 D_eo D_oe,
+//   M^+ = 1 - kappa^2 D_oe^+ D_eo^+ (dagger hops in the same order).
+// Iteration (sloppy precision; alpha, beta, gamma stay on the device):
+//   q = M p, alpha = gamma / |q|^2; x += alpha p; r -= alpha q (|r|^2 fused);
+//   s = M^+ r, gamma' = |s|^2, beta = gamma'/gamma; p = s + beta p.
+// The host reads only the |r|^2 history, once per chunk of iterations.  A
+// chunk is captured once as a HIP graph and replayed.  When the sloppy
+// residual of a right-hand side has fallen by `delta` since its last update
+// (or reached the tolerance, or maxiter) the FP64 accumulator takes x_lo and
+// the residual b' - M x is recomputed in FP64 (reliable update); p is kept
+// and s, gamma are recomputed from the new residual.  Two updates in a row
+// that fail to halve the FP64 residual raise the sloppy precision one step.
+// Finally psi_o = eta_o + kappa D_oe psi_e and the true residual
+// |eta - D psi| / |eta| is computed in FP64 with the whole-lattice operator.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "wl_host.h"
+
+namespace wl {
+
+static hipStream_t capture_stream()
+{
+    static hipStream_t cs = nullptr;
+    if (!cs && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = nullptr;
+    }
+    return cs;
+}
+
+struct Cg {
+    ExecSet &S;
+    hipStream_t s;
+    int recon;
+    double tol;
+    int maxiter;
+    double delta;
+    int sloppy;
+    bool use_graphs;
+
+    Field eta_e, eta_o, bp, xh, rh, t64, xo;  // FP64
+    Field xl, rl, p, q, sv, tl;               // sloppy
+    const double *c_plain = nullptr, *c_bp = nullptr, *c_M = nullptr, *c_res = nullptr, *c_tres = nullptr;
+
+    Cg(ExecSet &S_, hipStream_t s_) : S(S_), s(s_) {}
+
+    wl_status sloppy_fields()
+    {
+        WL_TRY(S.field("cg_xl", sloppy, &xl));
+        WL_TRY(S.field("cg_rl", sloppy, &rl));
+        WL_TRY(S.field("cg_p", sloppy, &p));
+        WL_TRY(S.field("cg_q", sloppy, &q));
+        WL_TRY(S.field("cg_s", sloppy, &sv));
+        WL_TRY(S.field("cg_t", sloppy, &tl));
+        return WL_OK;
+    }
+
+    wl_status setup()
+    {
+        WL_TRY(S.field("cg_eta_e", P_F64, &eta_e));
+        WL_TRY(S.field("cg_eta_o", P_F64, &eta_o));
+        WL_TRY(S.field("cg_bp", P_F64, &bp));
+        WL_TRY(S.field("cg_xh", P_F64, &xh));
+        WL_TRY(S.field("cg_rh", P_F64, &rh));
+        WL_TRY(S.field("cg_t64", P_F64, &t64));
+        WL_TRY(S.field("cg_xo", P_F64, &xo));
+        WL_TRY(sloppy_fields());
+        std::vector<double> cp, cb, cm, cr, ct;
+        for (auto &e : S.systems) {
+            const double k = e.kappa;
+            cp.insert(cp.end(), {0, 0, 0, 0, 1.0});
+            cb.insert(cb.end(), {1.0, 0, 0, 0, k});
+            cm.insert(cm.end(), {1.0, 0, 0, 0, -k * k});
+            cr.insert(cr.end(), {-1.0, 1.0, 0, 0, k * k});
+            ct.insert(ct.end(), {-1.0, 1.0, 0, 0, k});
+        }
+        WL_TRY(coef_table(S, cp, &c_plain));
+        WL_TRY(coef_table(S, cb, &c_bp));
+        WL_TRY(coef_table(S, cm, &c_M));
+        WL_TRY(coef_table(S, cr, &c_res));
+        WL_TRY(coef_table(S, ct, &c_tres));
+        return WL_OK;
+    }
+
+    Epi epi(const double *coef, int nx = 0, Field x0 = Field(), Field x1 = Field())
+    {
+        Epi e;
+        e.coef = coef;
+        e.nx = nx;
+        e.X[0] = x0;
+        e.X[1] = x1;
+        return e;
+    }
+
+    // out = M in (dag = false) or M^+ in (dag = true); tmp is an odd-parity field
+    wl_status apply_M(int prec, int rc, bool dag, const Field &out, const Field &in, const Field &tmp,
+                      const RedSpec &red, bool use_active = true)
+    {
+        WL_TRY(hop(S, prec, rc, dag, 1, tmp, in, epi(c_plain), no_red(), s, use_active));
+        WL_TRY(hop(S, prec, rc, dag, 0, out, tmp, epi(c_M, 1, in), red, s, use_active));
+        return WL_OK;
+    }
+
+    // rh = b' - M xh in FP64 with |rh|^2 into SC_RR
+    wl_status residual64(bool use_active = true)
+    {
+        WL_TRY(hop(S, P_F64, 18, false, 1, t64, xh, epi(c_plain), no_red(), s, use_active));
+        WL_TRY(hop(S, P_F64, 18, false, 0, rh, t64, epi(c_res, 2, xh, bp),
+                   red_spec(S, RED_STORE, S.scal(ExecSet::SC_RR)), s, use_active));
+        return WL_OK;
+    }
+
+    // one CGNR iteration in the sloppy precision; hist_row receives |r|^2
+    wl_status iteration(double *hist_row)
+    {
+        WL_TRY(apply_M(sloppy, recon, false, q, p, tl, red_spec(S, RED_ALPHA, nullptr)));
+        Field f[4] = {xl, p, rl, q};
+        WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(ExecSet::SC_ALPHA), red_spec(S, RED_STORE, hist_row), s));
+        WL_TRY(apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_BETA, nullptr)));
+        Field g[2] = {p, sv};
+        WL_TRY(blas(S, BL_XPAY, sloppy, g, 2, S.scal(ExecSet::SC_BETA), no_red(), s));
+        return WL_OK;
+    }
+
+    double iteration_bytes()
+    {
+        return 4 * hop_bytes(S, sloppy, recon, true) + 2 * blas_bytes(S, sloppy, 1, true) +
+               blas_bytes(S, sloppy, 6, true) + blas_bytes(S, sloppy, 3, true);
+    }
+
+    wl_status chunk(int k)
+    {
+        if (!use_graphs || prof().on) {
+            for (int j = 0; j < k; ++j) WL_TRY(iteration(S.hist + (size_t)j * S.nvec));
+            return WL_OK;
+        }
+        const std::string key = "cg/" + std::to_string(k) + "/" + std::to_string(sloppy) + "/" + std::to_string(recon);
+        auto it = S.graphs.find(key);
+        if (it == S.graphs.end()) {
+            hipStream_t cs = capture_stream();
+            if (!cs) return set_error(WL_ERR_HIP, "cannot create the capture stream");
+            const double saved = g_bytes_acc;
+            hipStream_t user = s;
+            s = cs;
+            WL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+            wl_status st = WL_OK;
+            for (int j = 0; j < k && st == WL_OK; ++j) st = iteration(S.hist + (size_t)j * S.nvec);
+            hipGraph_t g = nullptr;
+            hipError_t ce = hipStreamEndCapture(cs, &g);
+            s = user;
+            g_bytes_acc = saved;
+            if (st != WL_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (ce != hipSuccess) return set_error(WL_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+            hipGraphExec_t ex = nullptr;
+            hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ie != hipSuccess) return set_error(WL_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+            it = S.graphs.emplace(key, ex).first;
+        }
+        g_bytes_acc += k * iteration_bytes();
+        WL_HIP(hipGraphLaunch(it->second, s));
+        return WL_OK;
+    }
+};
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static int round_chunk(double k)
+{
+    static const int sizes[] = {2, 3, 4, 6, 8, 12, 16, 24, 32};
+    int best = sizes[0];
+    for (int c : sizes)
+        if (c <= k) best = c;
+    return best;
+}
+
+// Solve the systems of S for the canonical sources eta[i] into x[i] (guesses on entry).
+wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int recon, double tol, int maxiter,
+                 int sloppy, double delta, wl_solve_info *info, hipStream_t s)
+{
+    const double t0 = now_s();
+    g_bytes_acc = 0.0;
+    Cg cg(S, s);
+    cg.recon = recon;
+    cg.tol = tol;
+    cg.maxiter = maxiter;
+    cg.delta = delta;
+    cg.sloppy = sloppy;
+    const char *ge = getenv("WL_GRAPHS");
+    cg.use_graphs = !(ge && ge[0] == '0');
+    WL_TRY(cg.setup());
+    const int nv = S.nvec;
+    double *hp = S.h_pinned;  // [kHist * nv] history, then scalars
+
+    std::fill(S.h_active.begin(), S.h_active.end(), 1);
+    WL_TRY(S.upload_active(s));
+    WL_HIP(hipMemsetAsync(S.bad, 0, sizeof(int32_t) * nv, s));
+
+    // sources, |eta|^2, b', initial guess, first FP64 residual
+    WL_TRY(pack(S, eta, 0, cg.eta_e, s));
+    WL_TRY(pack(S, eta, 1, cg.eta_o, s));
+    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_e, 1, nullptr, red_spec(S, RED_STORE, S.scal(ExecSet::SC_ETA)), s));
+    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_o, 1, nullptr, red_spec(S, RED_ACCUM, S.scal(ExecSet::SC_ETA)), s));
+    WL_TRY(hop(S, P_F64, 18, false, 0, cg.bp, cg.eta_o, cg.epi(cg.c_bp, 1, cg.eta_e), no_red(), s));
+    WL_TRY(pack(S, (const double *const *)x, 0, cg.xh, s));
+    WL_TRY(cg.residual64());
+    WL_HIP(hipMemcpyAsync(hp, S.sc, sizeof(double) * ExecSet::SC_N * nv, hipMemcpyDeviceToHost, s));
+    WL_HIP(hipStreamSynchronize(s));
+    std::vector<double> eta_n(nv), rmax(nv), last_true(nv), target(nv);
+    std::vector<int> iters(nv, 0), updates(nv, 0), conv(nv, 0), done(nv, 0), stall(nv, 0);
+    std::vector<int> zero_src(nv, 0);
+    for (int v = 0; v < nv; ++v) {
+        eta_n[v] = std::sqrt(hp[ExecSet::SC_ETA * nv + v]);
+        const double r = std::sqrt(hp[ExecSet::SC_RR * nv + v]);
+        target[v] = tol * eta_n[v];
+        if (!std::isfinite(eta_n[v]) || !std::isfinite(r))
+            return set_error(WL_ERR_NONFINITE, "non-finite source or initial guess (rhs %d)", v);
+        if (eta_n[v] == 0.0) {
+            zero_src[v] = 1;
+            done[v] = conv[v] = 1;
+        } else if (r <= target[v]) {
+            done[v] = conv[v] = 1;
+        }
+        rmax[v] = last_true[v] = r;
+    }
+    // zero sources give x = 0
+    bool anyzero = false;
+    for (int v = 0; v < nv; ++v) {
+        S.h_active[v] = zero_src[v];
+        anyzero = anyzero || zero_src[v];
+    }
+    if (anyzero) {
+        WL_TRY(S.upload_active(s));
+        WL_TRY(blas(S, BL_ZERO, P_F64, &cg.xh, 1, nullptr, no_red(), s));
+    }
+    for (int v = 0; v < nv; ++v) S.h_active[v] = !done[v];
+    WL_TRY(S.upload_active(s));
+    bool any = false;
+    for (int v = 0; v < nv; ++v) any = any || !done[v];
+    int escalations = 0;
+    wl_status status = WL_OK;
+
+    if (any) {
+        WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+        WL_TRY(convert(S, cg.rl, cg.rh, s));
+        WL_TRY(cg.apply_M(cg.sloppy, recon, true, cg.sv, cg.rl, cg.tl, red_spec(S, RED_GAMMA, nullptr)));
+        Field cp[2] = {cg.p, cg.sv};
+        WL_TRY(blas(S, BL_COPY, cg.sloppy, cp, 2, nullptr, no_red(), s));
+        int k = 4;
+        bool first = true;
+        while (true) {
+            // the first chunk runs eagerly: it tunes launch shapes and builds layouts before capture
+            const bool graphs = cg.use_graphs;
+            if (first) cg.use_graphs = false;
+            WL_TRY(cg.chunk(k));
+            cg.use_graphs = graphs;
+            first = false;
+            WL_HIP(hipMemcpyAsync(hp, S.hist, sizeof(double) * k * nv, hipMemcpyDeviceToHost, s));
+            int32_t *hbad = (int32_t *)(hp + (size_t)ExecSet::kHist * nv);
+            WL_HIP(hipMemcpyAsync(hbad, S.bad, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, s));
+            WL_HIP(hipStreamSynchronize(s));
+            std::vector<int> upd(nv, 0);
+            bool anyupd = false;
+            double rate = 0.0;
+            int nrate = 0;
+            for (int v = 0; v < nv; ++v) {
+                if (done[v]) continue;
+                if (hbad[v]) {
+                    status = set_error(WL_ERR_NONFINITE, "non-finite value in the iteration (rhs %d)", v);
+                    break;
+                }
+                iters[v] += k;
+                double rfirst = 0, rlast = 0;
+                for (int j = 0; j < k; ++j) {
+                    const double r = std::sqrt(hp[(size_t)j * nv + v]);
+                    if (!std::isfinite(r)) {
+                        status = set_error(WL_ERR_NONFINITE, "non-finite residual (rhs %d)", v);
+                        break;
+                    }
+                    if (j == 0) rfirst = r;
+                    rlast = r;
+                    if (r <= target[v] || r < delta * rmax[v]) upd[v] = 1;
+                }
+                if (iters[v] >= maxiter) upd[v] = 1;
+                if (rfirst > 0 && rlast > 0 && k > 1) {
+                    rate += std::log10(rfirst / rlast) / (k - 1);
+                    ++nrate;
+                }
+                anyupd = anyupd || upd[v];
+            }
+            if (status != WL_OK) break;
+            if (anyupd) {
+                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v];
+                WL_TRY(S.upload_active(s));
+                Field ac[2] = {cg.xh, cg.xl};
+                WL_TRY(blas(S, BL_ACCUM, cg.sloppy, ac, 2, nullptr, no_red(), s));
+                WL_TRY(cg.residual64());
+                WL_HIP(hipMemcpyAsync(hp, S.scal(ExecSet::SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+                WL_HIP(hipStreamSynchronize(s));
+                bool stalled = false;
+                for (int v = 0; v < nv; ++v) {
+                    if (!upd[v]) continue;
+                    const double r = std::sqrt(hp[v]);
+                    ++updates[v];
+                    if (!std::isfinite(r)) {
+                        status = set_error(WL_ERR_NONFINITE, "non-finite FP64 residual (rhs %d)", v);
+                        break;
+                    }
+                    if (r <= target[v]) {
+                        done[v] = conv[v] = 1;
+                    } else if (iters[v] >= maxiter) {
+                        done[v] = 1;
+                    } else {
+                        stall[v] = r > 0.5 * last_true[v] ? stall[v] + 1 : 0;
+                        if (stall[v] >= 2) stalled = true;
+                    }
+                    last_true[v] = r;
+                    rmax[v] = r;
+                }
+                if (status != WL_OK) break;
+                if (stalled && cg.sloppy != P_F64) {
+                    // raise the sloppy precision: keep the search direction, restart the rest from FP64
+                    const int next = cg.sloppy == P_F32 ? P_F64 : P_F32;
+                    Field p_old = cg.p;
+                    cg.sloppy = next;
+                    WL_TRY(cg.sloppy_fields());
+                    for (int v = 0; v < nv; ++v) S.h_active[v] = !done[v];
+                    WL_TRY(S.upload_active(s));
+                    WL_TRY(convert(S, cg.p, p_old, s));
+                    WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+                    for (int v = 0; v < nv; ++v)
+                        if (!done[v]) {
+                            upd[v] = 1;
+                            stall[v] = 0;
+                        }
+                    ++escalations;
+                }
+                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v] && !done[v];
+                WL_TRY(S.upload_active(s));
+                WL_TRY(convert(S, cg.rl, cg.rh, s));
+                WL_TRY(cg.apply_M(cg.sloppy, recon, true, cg.sv, cg.rl, cg.tl, red_spec(S, RED_GAMMA, nullptr)));
+            }
+            bool left = false;
+            for (int v = 0; v < nv; ++v) {
+                S.h_active[v] = !done[v];
+                left = left || !done[v];
+            }
+            if (!left) break;
+            WL_TRY(S.upload_active(s));
+            // next chunk spans about one reliable-update interval
+            if (nrate > 0 && rate / nrate > 1e-3) {
+                const double want = std::log10(1.0 / delta) / (rate / nrate);
+                k = round_chunk(std::min(32.0, std::max(2.0, want)));
+            }
+        }
+    }
+
+    // odd sites, true residual with the whole-lattice operator, unpack
+    std::fill(S.h_active.begin(), S.h_active.end(), 1);
+    WL_TRY(S.upload_active(s));
+    WL_TRY(hop(S, P_F64, 18, false, 1, cg.xo, cg.xh, cg.epi(cg.c_bp, 1, cg.eta_o), no_red(), s));
+    WL_TRY(hop(S, P_F64, 18, false, 0, cg.rh, cg.xo, cg.epi(cg.c_tres, 2, cg.xh, cg.eta_e),
+               red_spec(S, RED_STORE, S.scal(ExecSet::SC_RR)), s));
+    WL_TRY(hop(S, P_F64, 18, false, 1, cg.t64, cg.xh, cg.epi(cg.c_tres, 2, cg.xo, cg.eta_o),
+               red_spec(S, RED_ACCUM, S.scal(ExecSet::SC_RR)), s));
+    WL_TRY(unpack(S, x, 0, cg.xh, s));
+    WL_TRY(unpack(S, x, 1, cg.xo, s));
+    WL_HIP(hipMemcpyAsync(hp, S.scal(ExecSet::SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    WL_HIP(hipStreamSynchronize(s));
+    const double t1 = now_s();
+    bool allconv = true;
+    for (int v = 0; v < nv; ++v) {
+        const double tr = eta_n[v] > 0 ? std::sqrt(hp[v]) / eta_n[v] : 0.0;
+        if (info) {
+            info[v].iters = iters[v];
+            info[v].reliable_updates = updates[v];
+            info[v].converged = conv[v] && std::isfinite(tr);
+            info[v].precision_escalations = escalations;
+            info[v].true_resid = tr;
+            info[v].seconds = t1 - t0;
+            info[v].gbytes = g_bytes_acc * 1e-9;
+        }
+        allconv = allconv && conv[v];
+    }
+    if (status != WL_OK) return status;
+    if (!allconv) return set_error(WL_ERR_NOCONV, "maxiter %d reached before tol %g", maxiter, tol);
+    return WL_OK;
+}
+
+}  // namespace wl
+
+using namespace wl;
+
+static wl_status check_solver_args(double tol, int32_t maxiter, wl_prec sloppy, int32_t recon, double delta)
+{
+    if (!(tol > 0) || !std::isfinite(tol)) return set_error(WL_ERR_ARG, "tol must be > 0");
+    if (maxiter < 1) return set_error(WL_ERR_ARG, "maxiter must be >= 1");
+    if (!(delta > 0 && delta < 1)) return set_error(WL_ERR_ARG, "delta must be in (0, 1)");
+    if (!prec_recon_ok(sloppy, recon)) return set_error(WL_ERR_PREC, "unsupported sloppy precision %d / recon %d", sloppy, recon);
+    return WL_OK;
+}
+
+namespace wl {
+wl_status check_gauge(wl_gauge U);
+wl_status check_field(const void *p, wl_gauge U, int nrhs, const char *what);
+}  // namespace wl
+
+extern "C" {
+
+wl_status wilson_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double tol,
+                    int32_t maxiter, wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info, void *stream)
+{
+    clear_error();
+    WL_TRY(check_gauge(U));
+    if (nrhs < 1) return set_error(WL_ERR_ARG, "nrhs = %d must be >= 1", nrhs);
+    if (!(kappa > 0) || !std::isfinite(kappa)) return set_error(WL_ERR_ARG, "kappa must be > 0 and finite");
+    WL_TRY(check_solver_args(tol, maxiter, sloppy, recon, delta));
+    WL_TRY(check_field(eta, U, nrhs, "eta"));
+    WL_TRY(check_field(x, U, nrhs, "x"));
+    ExecSet *S = nullptr;
+    WL_TRY(get_set({SysEntry{U, nrhs, kappa}}, &S));
+    const double *e[1] = {eta};
+    double *xx[1] = {x};
+    return run_cg(*S, e, xx, recon, tol, maxiter, sloppy, delta, info, (hipStream_t)stream);
+}
+
+wl_status wilson_cg_multi(int32_t nsys, const wl_gauge *U, const double *const *eta, double *const *x,
+                          const int32_t *nrhs, const double *kappa, double tol, int32_t maxiter, wl_prec sloppy,
+                          int32_t recon, double delta, wl_solve_info *info, void *stream)
+{
+    clear_error();
+    if (nsys < 1 || nsys > kMaxSys) return set_error(WL_ERR_ARG, "nsys must be in [1, %d]", kMaxSys);
+    if (!U || !eta || !x || !nrhs || !kappa) return set_error(WL_ERR_ARG, "null array argument");
+    WL_TRY(check_solver_args(tol, maxiter, sloppy, recon, delta));
+    std::vector<SysEntry> sys;
+    for (int i = 0; i < nsys; ++i) {
+        WL_TRY(check_gauge(U[i]));
+        if (nrhs[i] < 1) return set_error(WL_ERR_ARG, "nrhs[%d] must be >= 1", i);
+        if (!(kappa[i] > 0) || !std::isfinite(kappa[i])) return set_error(WL_ERR_ARG, "kappa[%d] must be > 0", i);
+        WL_TRY(check_field(eta[i], U[i], nrhs[i], "eta[i]"));
+        WL_TRY(check_field(x[i], U[i], nrhs[i], "x[i]"));
+        sys.push_back(SysEntry{U[i], nrhs[i], kappa[i]});
+    }
+    ExecSet *S = nullptr;
+    WL_TRY(get_set(sys, &S));
+    return run_cg(*S, eta, x, recon, tol, maxiter, sloppy, delta, info, (hipStream_t)stream);
+}
+
+}  // extern "C"

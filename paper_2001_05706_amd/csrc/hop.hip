@@ -1,0 +1,100 @@
+// hop.hip -- the single-parity Wilson hopping kernel (the D-slash of Table 2)
+// with a fused linear-combination epilogue and optional fused |out|^2.
+//
+// One thread per output site of one vector.  Per direction the neighbour
+// spinor is spin-projected to two components (12 flop), both are multiplied
+// by the link (2 x 66 flop) rebuilt from 12 reals when recon = 12, and the
+// result is spin-reconstructed into the accumulator (24 flop): 1320 flop per
+// site.  Links are read with non-temporal loads (each is used once per hop);
+// neighbour spinors are shared by up to 8 output sites through L2, which the
+// XCD-aware block order keeps on one die.
+#include "wl_reduce.h"
+#include "wl_kernels.h"
+
+namespace wl {
+
+// Occupancy target per storage precision: the hop is bound by memory latency
+// and bandwidth, so the register budget is capped to keep enough waves in
+// flight (FP32/FP16/BF16: 4 waves per SIMD, i.e. <= 128 VGPRs; FP64: 3).
+template <int SP> struct HopOcc { static constexpr int waves = SP == P_F64 ? 3 : 4; };
+
+template <int SP, int GP, int R, bool DAG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopOcc<SP>::waves))) void k_hop(HopArgs a)
+{
+    using T = typename SpinorFmt<SP>::real;
+    using CH = typename SpinorFmt<SP>::chunk;
+    constexpr int NC = SpinorFmt<SP>::nchunk;
+
+    const int lb = xcd_remap(blockIdx.x, a.nblocks);
+    const BlkMap bm = a.map[lb];
+    if (a.active && !a.active[bm.v]) return;
+    const VecDesc vd = a.vec[bm.v];
+    const SysDesc sd = a.sys[vd.sys];
+    const int cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
+    const size_t voff = (size_t)vd.site_off * NC;
+
+    double nrm = 0.0;
+    if (cb < sd.Vh) {
+        HopSite hs;
+        hs.in = (const CH *)a.in + voff;
+        hs.in_norm = a.in_norm ? a.in_norm + vd.site_off : nullptr;
+        hs.stride = sd.stride;
+        hs.gauge = sd.gauge;
+        hs.gstride = sd.gstride;
+        T acc[24];
+        hop_site<SP, GP, R, DAG>(sd, hs, a.parity, cb, acc);
+
+        const double *cf = a.epi.coef + vd.sys * 5;
+        const T c = (T)cf[4];
+        T o[24];
+        if (a.epi.nx >= 1) {
+            T x[24];
+            load_spinor<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
+                            sd.stride, cb, x);
+            const T a0 = (T)cf[0];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = a0 * x[k] + c * acc[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] = c * acc[k];
+        }
+        if (a.epi.g5) {
+#pragma unroll
+            for (int k = 12; k < 24; ++k) o[k] = -o[k];
+        }
+        for (int j = 1; j < a.epi.nx; ++j) {
+            T x[24];
+            load_spinor<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+                            sd.stride, cb, x);
+            const T aj = (T)cf[j];
+#pragma unroll
+            for (int k = 0; k < 24; ++k) o[k] += aj * x[k];
+        }
+        store_spinor<SP>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
+        if (a.red.kind != RED_NONE) nrm = site_norm2(o);
+    }
+    if (a.red.kind != RED_NONE) block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
+}
+
+template <int SP, int GP, int R>
+static hipError_t launch_hop_t(bool dag, const HopArgs &a, int block, hipStream_t s)
+{
+    if (dag)
+        hipLaunchKernelGGL((k_hop<SP, GP, R, true>), dim3(a.nblocks), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_hop<SP, GP, R, false>), dim3(a.nblocks), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_hop(int prec, int recon, bool dag, const HopArgs &a, int block, hipStream_t s)
+{
+    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(dag, a, block, s);
+    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(dag, a, block, s);
+    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(dag, a, block, s);
+    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(dag, a, block, s);
+    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(dag, a, block, s);
+    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(dag, a, block, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wl

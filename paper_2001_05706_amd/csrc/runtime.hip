@@ -1,0 +1,936 @@
+// runtime.hip -- host runtime: errors, validation, gauge handles, execution
+// sets, launch helpers, the block-size autotuner, kernel timing, the D-slash
+// entry point and the measurement entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "wl_host.h"
+
+namespace wl {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local char t_err[512];
+thread_local double g_bytes_acc = 0.0;
+
+wl_status set_error(wl_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_err, sizeof(t_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+void clear_error() { t_err[0] = 0; }
+
+bool device_range_ok(const void *p, size_t bytes)
+{
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;  // treated as not device memory
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (const char *)p + bytes <= (const char *)base + size;
+}
+
+// ------------------------------------------------------------------ precision helpers
+
+int spinor_site_bytes(int prec)
+{
+    switch (prec) {
+    case P_F64: return 192;
+    case P_F32: return 96;
+    case P_F16:
+    case P_BF16: return 52;
+    }
+    return 0;
+}
+
+int chunk_bytes(int prec) { return prec == P_F64 || prec == P_F32 || prec == P_F16 || prec == P_BF16 ? 16 : 0; }
+int nchunks(int prec) { return prec == P_F64 ? 12 : prec == P_F32 ? 6 : 3; }
+
+bool prec_recon_ok(int prec, int recon)
+{
+    if (recon == 12) return prec >= P_F64 && prec <= P_BF16;
+    if (recon == 18) return prec == P_F64 || prec == P_F32;
+    return false;
+}
+
+int link_bytes(int prec, int recon)
+{
+    const int reals = recon;
+    return reals * (prec == P_F64 ? 8 : prec == P_F32 ? 4 : 2);
+}
+
+static int link_chunk_bytes(int prec, int recon)
+{
+    if (prec == P_F64) return 16;
+    if (prec == P_F32) return recon == 18 ? 8 : 16;
+    return 8;
+}
+static int link_nchunks(int prec, int recon)
+{
+    if (prec == P_F64) return recon == 18 ? 9 : 6;
+    if (prec == P_F32) return recon == 18 ? 9 : 3;
+    return 3;
+}
+
+// ------------------------------------------------------------------ kernel timing
+
+Prof &prof()
+{
+    static Prof p;
+    return p;
+}
+
+void prof_collect()
+{
+    Prof &p = prof();
+    for (size_t i = 0; i < p.pending.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.pending[i].second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.pending[i].first, p.pending[i].second) == hipSuccess) {
+            p.ms += ms;
+            p.launches += 1;
+            p.gbytes += p.pending_bytes[i];
+        }
+        (void)hipEventDestroy(p.pending[i].first);
+        (void)hipEventDestroy(p.pending[i].second);
+    }
+    p.pending.clear();
+    p.pending_bytes.clear();
+}
+
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return st == hipStreamCaptureStatusActive;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tuned;
+
+int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream_t s,
+                const std::function<hipError_t(int)> &run)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) return it->second;
+    }
+    const int fallback = 256;
+    const char *env = getenv("WL_TUNE");
+    if ((env && env[0] == '0') || capturing(s)) return fallback;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fallback;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fallback;
+    }
+    int best = fallback;
+    float best_ms = 1e30f;
+    for (int B : cands) {
+        if (run(B) != hipSuccess) {  // warm-up; a failed launch rules the candidate out
+            (void)hipGetLastError();
+            continue;
+        }
+        (void)hipEventRecord(e0, s);
+        const int reps = 3;
+        bool ok = true;
+        for (int r = 0; r < reps; ++r) ok = ok && run(B) == hipSuccess;
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best = B;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+    return best;
+}
+
+}  // namespace wl
+
+// ------------------------------------------------------------------ gauge handle
+
+using namespace wl;
+
+wl_gauge_s::~wl_gauge_s()
+{
+    (void)hipFree(U);
+    for (auto &a : packed)
+        for (auto &p : a) (void)hipFree(p);
+}
+
+namespace wl {
+
+wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const void **out)
+{
+    if (!prec_recon_ok(prec, recon)) return set_error(WL_ERR_PREC, "unsupported precision %d / recon %d", prec, recon);
+    void *&p = g->packed[prec][recon == 12 ? 1 : 0];
+    if (!p) {
+        const size_t bytes = (size_t)2 * 4 * link_nchunks(prec, recon) * g->geom.gstride * link_chunk_bytes(prec, recon);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return set_error(WL_ERR_NOMEM, "cannot allocate %zu bytes of packed links", bytes);
+        }
+        WL_HIP(hipMemsetAsync(p, 0, bytes, s));
+        WL_HIP(launch_pack_gauge(prec, recon, g->U, p, g->geom, s));
+    }
+    *out = p;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ execution sets
+
+ExecSet::ExecSet(const std::vector<SysEntry> &s) : systems(s) {}
+
+ExecSet::~ExecSet()
+{
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : fields) {
+        (void)hipFree(kv.second.p);
+        (void)hipFree(kv.second.n);
+    }
+    for (auto &kv : coefs) (void)hipFree(kv.second);
+    for (auto &kv : d_sys) (void)hipFree(kv.second);
+    for (auto &kv : layouts) {
+        (void)hipFree(kv.second.d_vec);
+        (void)hipFree(kv.second.d_map);
+    }
+    (void)hipFree(d_active);
+    (void)hipFree(partials);
+    (void)hipFree(counters);
+    (void)hipFree(sc);
+    (void)hipFree(bad);
+    (void)hipFree(hist);
+    (void)hipHostFree(h_pinned);
+}
+
+#define WL_ALLOC(ptr, bytes)                                                              \
+    do {                                                                                  \
+        if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                          \
+            (void)hipGetLastError();                                                      \
+            (ptr) = nullptr;                                                              \
+            return set_error(WL_ERR_NOMEM, "cannot allocate %zu bytes", (size_t)(bytes)); \
+        }                                                                                 \
+    } while (0)
+
+wl_status ExecSet::init()
+{
+    if ((int)systems.size() > kMaxSys) return set_error(WL_ERR_ARG, "at most %d systems per set", kMaxSys);
+    nvec = 0;
+    total_sites = 0;
+    max_pslots = 0;
+    for (size_t i = 0; i < systems.size(); ++i) {
+        const SysDesc &g = systems[i].g->geom;
+        for (int r = 0; r < systems[i].nrhs; ++r) {
+            VecDesc v{};
+            v.sys = (int)i;
+            v.rhs = r;
+            v.site_off = (int32_t)total_sites;
+            vec.push_back(v);
+            total_sites += g.stride;
+            max_pslots += (g.Vh + 63) / 64;
+            ++nvec;
+        }
+    }
+    if (total_sites > (size_t)INT32_MAX / 16) return set_error(WL_ERR_GEOM, "set too large");
+    h_active.assign(nvec, 1);
+    WL_ALLOC(d_active, sizeof(int32_t) * nvec);
+    WL_ALLOC(partials, sizeof(double) * max_pslots);
+    WL_ALLOC(counters, sizeof(uint32_t) * nvec);
+    WL_ALLOC(sc, sizeof(double) * SC_N * nvec);
+    WL_ALLOC(bad, sizeof(int32_t) * nvec);
+    WL_ALLOC(hist, sizeof(double) * kHist * nvec);
+    if (hipHostMalloc((void **)&h_pinned, sizeof(double) * (kHist + SC_N + 1) * nvec + 64, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        h_pinned = nullptr;
+        return set_error(WL_ERR_NOMEM, "cannot allocate pinned host memory");
+    }
+    WL_HIP(hipMemcpy(d_active, h_active.data(), sizeof(int32_t) * nvec, hipMemcpyHostToDevice));
+    WL_HIP(hipMemset(counters, 0, sizeof(uint32_t) * nvec));
+    WL_HIP(hipMemset(sc, 0, sizeof(double) * SC_N * nvec));
+    WL_HIP(hipMemset(bad, 0, sizeof(int32_t) * nvec));
+    WL_HIP(hipMemset(hist, 0, sizeof(double) * kHist * nvec));
+    return WL_OK;
+}
+
+wl_status ExecSet::upload_active(hipStream_t s)
+{
+    int32_t *h = (int32_t *)(h_pinned + (size_t)(kHist + SC_N) * nvec);
+    // the previous upload from this buffer has completed: callers synchronise between uploads
+    std::copy(h_active.begin(), h_active.end(), h);
+    WL_HIP(hipMemcpyAsync(d_active, h, sizeof(int32_t) * nvec, hipMemcpyHostToDevice, s));
+    WL_HIP(hipStreamSynchronize(s));
+    return WL_OK;
+}
+
+wl_status ExecSet::sys_table(int prec, int recon, hipStream_t s, const SysDesc **out)
+{
+    auto key = std::make_pair(prec, recon);
+    auto it = d_sys.find(key);
+    if (it != d_sys.end()) {
+        *out = it->second;
+        return WL_OK;
+    }
+    std::vector<SysDesc> h(systems.size());
+    for (size_t i = 0; i < systems.size(); ++i) {
+        h[i] = systems[i].g->geom;
+        h[i].gauge = nullptr;  // prec < 0: geometry only
+        if (prec >= 0) WL_TRY(gauge_packed(systems[i].g, prec, recon, s, &h[i].gauge));
+    }
+    SysDesc *d = nullptr;
+    WL_ALLOC(d, sizeof(SysDesc) * h.size());
+    WL_HIP(hipMemcpy(d, h.data(), sizeof(SysDesc) * h.size(), hipMemcpyHostToDevice));
+    d_sys[key] = d;
+    *out = d;
+    return WL_OK;
+}
+
+wl_status ExecSet::layout(int B, const Layout **out)
+{
+    auto it = layouts.find(B);
+    if (it != layouts.end()) {
+        *out = &it->second;
+        return WL_OK;
+    }
+    Layout L;
+    L.B = B;
+    std::vector<VecDesc> hv = vec;
+    std::vector<BlkMap> map;
+    int ps = 0, vbase = 0;
+    for (size_t i = 0; i < systems.size(); ++i) {
+        const int nrhs = systems[i].nrhs;
+        const int nb = (systems[i].g->geom.Vh + B - 1) / B;
+        for (int r = 0; r < nrhs; ++r) {
+            hv[vbase + r].nblk = nb;
+            hv[vbase + r].pslot0 = ps;
+            ps += nb;
+        }
+        // logical order (system, site block, rhs): right-hand sides sharing links are adjacent
+        for (int b = 0; b < nb; ++b)
+            for (int r = 0; r < nrhs; ++r) map.push_back(BlkMap{vbase + r, b});
+        vbase += nrhs;
+    }
+    L.nblocks = (int)map.size();
+    L.npslots = ps;
+    if (ps > max_pslots) return set_error(WL_ERR_ARG, "block size %d below the supported minimum", B);
+    WL_ALLOC(L.d_vec, sizeof(VecDesc) * hv.size());
+    WL_ALLOC(L.d_map, sizeof(BlkMap) * map.size());
+    WL_HIP(hipMemcpy(L.d_vec, hv.data(), sizeof(VecDesc) * hv.size(), hipMemcpyHostToDevice));
+    WL_HIP(hipMemcpy(L.d_map, map.data(), sizeof(BlkMap) * map.size(), hipMemcpyHostToDevice));
+    layouts[B] = L;
+    *out = &layouts[B];
+    return WL_OK;
+}
+
+wl_status ExecSet::field(const std::string &name, int prec, Field *out)
+{
+    const std::string key = name + "#" + std::to_string(prec);
+    auto it = fields.find(key);
+    if (it != fields.end()) {
+        *out = it->second;
+        return WL_OK;
+    }
+    Field f;
+    f.prec = prec;
+    const size_t bytes = total_sites * (size_t)nchunks(prec) * chunk_bytes(prec);
+    WL_ALLOC(f.p, bytes);
+    WL_HIP(hipMemset(f.p, 0, bytes));
+    if (prec == P_F16 || prec == P_BF16) {
+        if (hipMalloc((void **)&f.n, total_sites * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(f.p);
+            return set_error(WL_ERR_NOMEM, "cannot allocate norms");
+        }
+        WL_HIP(hipMemset(f.n, 0, total_sites * sizeof(float)));
+    }
+    fields[key] = f;
+    *out = f;
+    return WL_OK;
+}
+
+static std::mutex g_sets_mu;
+static std::vector<std::unique_ptr<ExecSet>> g_sets;
+
+wl_status get_set(const std::vector<SysEntry> &systems, ExecSet **out)
+{
+    std::lock_guard<std::mutex> lk(g_sets_mu);
+    for (auto &S : g_sets) {
+        if (S->systems.size() != systems.size()) continue;
+        bool same = true;
+        for (size_t i = 0; i < systems.size() && same; ++i)
+            same = S->systems[i].g == systems[i].g && S->systems[i].nrhs == systems[i].nrhs;
+        if (same) {
+            for (size_t i = 0; i < systems.size(); ++i) S->systems[i].kappa = systems[i].kappa;
+            *out = S.get();
+            return WL_OK;
+        }
+    }
+    std::unique_ptr<ExecSet> S(new ExecSet(systems));
+    WL_TRY(S->init());
+    *out = S.get();
+    g_sets.push_back(std::move(S));
+    return WL_OK;
+}
+
+void drop_sets_of(wl_gauge g)
+{
+    std::lock_guard<std::mutex> lk(g_sets_mu);
+    g_sets.erase(std::remove_if(g_sets.begin(), g_sets.end(),
+                                [g](const std::unique_ptr<ExecSet> &S) {
+                                    for (auto &e : S->systems)
+                                        if (e.g == g) return true;
+                                    return false;
+                                }),
+                 g_sets.end());
+}
+
+wl_status coef_table(ExecSet &S, const std::vector<double> &c, const double **out)
+{
+    auto it = S.coefs.find(c);
+    if (it != S.coefs.end()) {
+        *out = it->second;
+        return WL_OK;
+    }
+    double *d = nullptr;
+    WL_ALLOC(d, sizeof(double) * c.size());
+    WL_HIP(hipMemcpy(d, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice));
+    S.coefs[c] = d;
+    *out = d;
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ launch helpers
+
+RedSpec no_red()
+{
+    RedSpec r{};
+    r.kind = RED_NONE;
+    return r;
+}
+
+RedSpec red_spec(ExecSet &S, int kind, double *dst)
+{
+    RedSpec r{};
+    r.kind = kind;
+    r.partials = S.partials;
+    r.counters = S.counters;
+    r.dst = dst;
+    r.gam = S.scal(ExecSet::SC_GAM);
+    r.alpha = S.scal(ExecSet::SC_ALPHA);
+    r.beta = S.scal(ExecSet::SC_BETA);
+    r.bad = S.bad;
+    return r;
+}
+
+static bool any_active_in(const ExecSet &S, int sys, bool use_active)
+{
+    for (int v = 0; v < S.nvec; ++v)
+        if (S.vec[v].sys == sys && (!use_active || S.h_active[v])) return true;
+    return false;
+}
+
+double hop_bytes(const ExecSet &S, int prec, int recon, bool use_active)
+{
+    double b = 0;
+    for (size_t i = 0; i < S.systems.size(); ++i)
+        if (any_active_in(S, (int)i, use_active)) b += 8.0 * link_bytes(prec, recon) * S.systems[i].g->geom.Vh;
+    for (int v = 0; v < S.nvec; ++v)
+        if (!use_active || S.h_active[v]) b += 2.0 * spinor_site_bytes(prec) * S.systems[S.vec[v].sys].g->geom.Vh;
+    return b;
+}
+
+double blas_bytes(const ExecSet &S, int prec, int passes, bool use_active)
+{
+    double b = 0;
+    for (int v = 0; v < S.nvec; ++v)
+        if (!use_active || S.h_active[v]) b += (double)passes * spinor_site_bytes(prec) * S.systems[S.vec[v].sys].g->geom.Vh;
+    return b;
+}
+
+static std::string set_sig(const ExecSet &S)
+{
+    return std::to_string(S.nvec) + ":" + std::to_string(S.total_sites);
+}
+
+wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
+              const RedSpec &red, hipStream_t s, bool use_active)
+{
+    const SysDesc *sysd = nullptr;
+    WL_TRY(S.sys_table(prec, recon, s, &sysd));
+    auto mk = [&](const Layout *L, const RedSpec &rs) {
+        HopArgs a{};
+        a.sys = sysd;
+        a.vec = L->d_vec;
+        a.map = L->d_map;
+        a.active = use_active ? S.d_active : nullptr;
+        a.nblocks = L->nblocks;
+        a.parity = par;
+        a.in = in.p;
+        a.in_norm = in.n;
+        a.out = out.p;
+        a.out_norm = out.n;
+        a.epi.nx = e.nx;
+        a.epi.g5 = e.g5;
+        a.epi.coef = e.coef;
+        for (int j = 0; j < 4; ++j) {
+            a.epi.X[j] = e.X[j].p;
+            a.epi.Xn[j] = e.X[j].n;
+        }
+        a.red = rs;
+        return a;
+    };
+    const std::string key = "hop/" + std::to_string(prec) + "/" + std::to_string(recon) + "/" + std::to_string(dag) +
+                            "/" + set_sig(S);
+    const int B = tuned_block(key, {64, 128, 256, 512}, s, [&](int b) -> hipError_t {
+        const Layout *L = nullptr;
+        if (S.layout(b, &L) != WL_OK) return hipErrorOutOfMemory;
+        return launch_hop(prec, recon, dag, mk(L, no_red()), b, s);
+    });
+    const Layout *L = nullptr;
+    WL_TRY(S.layout(B, &L));
+    const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active);
+    g_bytes_acc += bytes;
+    Prof &P = prof();
+    const bool timed = P.on && !capturing(s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        WL_HIP(hipEventCreate(&e0));
+        WL_HIP(hipEventCreate(&e1));
+        WL_HIP(hipEventRecord(e0, s));
+    }
+    WL_HIP(launch_hop(prec, recon, dag, mk(L, red), B, s));
+    if (timed) {
+        WL_HIP(hipEventRecord(e1, s));
+        P.pending.push_back({e0, e1});
+        P.pending_bytes.push_back(bytes * 1e-9);
+    }
+    return WL_OK;
+}
+
+static const int kBlasBlock = 256;
+
+wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
+               hipStream_t s, bool use_active)
+{
+    const SysDesc *sysd = nullptr;
+    WL_TRY(S.sys_table(-1, 0, s, &sysd));  // geometry only
+    const Layout *L = nullptr;
+    WL_TRY(S.layout(kBlasBlock, &L));
+    BlasArgs a{};
+    a.sys = sysd;
+    a.vec = L->d_vec;
+    a.map = L->d_map;
+    a.active = use_active ? S.d_active : nullptr;
+    a.nblocks = L->nblocks;
+    for (int j = 0; j < nf; ++j) {
+        a.f[j] = f[j].p;
+        a.fn[j] = f[j].n;
+    }
+    a.s0 = s0;
+    a.red = red;
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2};
+    if (op == BL_ACCUM)
+        g_bytes_acc += blas_bytes(S, P_F64, 2, use_active) + blas_bytes(S, prec, 2, use_active);
+    else
+        g_bytes_acc += blas_bytes(S, prec, passes[op], use_active);
+    WL_HIP(launch_blas(op, prec, a, kBlasBlock, s));
+    return WL_OK;
+}
+
+wl_status convert(ExecSet &S, const Field &dst, const Field &src, hipStream_t s, bool use_active)
+{
+    const SysDesc *sysd = nullptr;
+    WL_TRY(S.sys_table(-1, 0, s, &sysd));
+    const Layout *L = nullptr;
+    WL_TRY(S.layout(kBlasBlock, &L));
+    BlasArgs a{};
+    a.sys = sysd;
+    a.vec = L->d_vec;
+    a.map = L->d_map;
+    a.active = use_active ? S.d_active : nullptr;
+    a.nblocks = L->nblocks;
+    a.f[0] = dst.p;
+    a.fn[0] = dst.n;
+    a.f[1] = src.p;
+    a.fn[1] = src.n;
+    a.red = no_red();
+    g_bytes_acc += blas_bytes(S, dst.prec, 1, use_active) + blas_bytes(S, src.prec, 1, use_active);
+    WL_HIP(launch_convert(dst.prec, src.prec, a, kBlasBlock, s));
+    return WL_OK;
+}
+
+static wl_status pack_args(ExecSet &S, const void *const *canon, int parity, const Field &f, hipStream_t s,
+                           PackArgs *a)
+{
+    const SysDesc *sysd = nullptr;
+    WL_TRY(S.sys_table(-1, 0, s, &sysd));
+    const Layout *L = nullptr;
+    WL_TRY(S.layout(kBlasBlock, &L));
+    *a = PackArgs{};
+    a->sys = sysd;
+    a->vec = L->d_vec;
+    a->map = L->d_map;
+    a->nblocks = L->nblocks;
+    a->parity = parity;
+    a->f = f.p;
+    a->fn = f.n;
+    for (size_t i = 0; i < S.systems.size(); ++i) a->canon[i] = (const double *)canon[i];
+    return WL_OK;
+}
+
+wl_status pack(ExecSet &S, const double *const *canon, int parity, const Field &f, hipStream_t s)
+{
+    PackArgs a;
+    WL_TRY(pack_args(S, (const void *const *)canon, parity, f, s, &a));
+    g_bytes_acc += blas_bytes(S, P_F64, 1, false) + blas_bytes(S, f.prec, 1, false);
+    WL_HIP(launch_pack_spinor(f.prec, a, kBlasBlock, s));
+    return WL_OK;
+}
+
+wl_status unpack(ExecSet &S, double *const *canon, int parity, const Field &f, hipStream_t s)
+{
+    PackArgs a;
+    WL_TRY(pack_args(S, (const void *const *)canon, parity, f, s, &a));
+    g_bytes_acc += blas_bytes(S, P_F64, 1, false) + blas_bytes(S, f.prec, 1, false);
+    WL_HIP(launch_unpack_spinor(f.prec, a, kBlasBlock, s));
+    return WL_OK;
+}
+
+wl_status zero_canon(ExecSet &S, double *const *canon, int parity, hipStream_t s)
+{
+    PackArgs a;
+    Field none;
+    WL_TRY(pack_args(S, (const void *const *)canon, parity, none, s, &a));
+    g_bytes_acc += blas_bytes(S, P_F64, 1, false);
+    WL_HIP(launch_zero_canon(a, kBlasBlock, s));
+    return WL_OK;
+}
+
+// ------------------------------------------------------------------ validation helpers
+
+wl_status check_gauge(wl_gauge U)
+{
+    if (!U) return set_error(WL_ERR_ARG, "null gauge handle");
+    return WL_OK;
+}
+
+wl_status check_field(const void *p, wl_gauge U, int nrhs, const char *what)
+{
+    const size_t bytes = (size_t)nrhs * 2 * U->geom.Vh * 24 * sizeof(double);
+    if (!p) return set_error(WL_ERR_ARG, "%s is NULL", what);
+    if (!device_range_ok(p, bytes))
+        return set_error(WL_ERR_ARG, "%s is not a device allocation of at least %zu bytes", what, bytes);
+    return WL_OK;
+}
+
+}  // namespace wl
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char *wl_status_string(wl_status s)
+{
+    switch (s) {
+    case WL_OK: return "ok";
+    case WL_ERR_ARG: return "invalid argument";
+    case WL_ERR_GEOM: return "invalid lattice geometry";
+    case WL_ERR_PREC: return "unsupported precision or compression";
+    case WL_ERR_NOMEM: return "out of device memory";
+    case WL_ERR_HIP: return "HIP runtime error";
+    case WL_ERR_NOCONV: return "solver did not converge";
+    case WL_ERR_NONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char *wl_last_error(void) { return t_err; }
+
+wl_status wl_gauge_create(const wl_geom *geom, const double *U_dev, void *stream, wl_gauge *out)
+{
+    clear_error();
+    if (!geom || !out) return set_error(WL_ERR_ARG, "null geometry or output handle");
+    *out = nullptr;
+    size_t V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = geom->L[mu];
+        if (L < 2 || (L & 1)) return set_error(WL_ERR_GEOM, "L[%d] = %d must be even and >= 2", mu, L);
+        V *= (size_t)L;
+    }
+    if (V / 2 > (size_t)(1 << 26)) return set_error(WL_ERR_GEOM, "lattice of %zu sites is too large", V);
+    if (geom->antiperiodic_t != 0 && geom->antiperiodic_t != 1)
+        return set_error(WL_ERR_ARG, "antiperiodic_t must be 0 or 1");
+    const size_t bytes = V * 4 * 18 * sizeof(double);
+    if (!device_range_ok(U_dev, bytes))
+        return set_error(WL_ERR_ARG, "links are not a device allocation of at least %zu bytes", bytes);
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<wl_gauge_s> g(new wl_gauge_s());
+    SysDesc &d = g->geom;
+    d = SysDesc{};
+    for (int mu = 0; mu < 4; ++mu) d.L[mu] = geom->L[mu];
+    d.Lxh = geom->L[0] / 2;
+    d.Vh = (int)(V / 2);
+    d.stride = padded(d.Vh);
+    d.gstride = d.stride;
+    d.tap = geom->antiperiodic_t;
+    WL_HIP(hipGetDevice(&g->device));
+    if (hipMalloc((void **)&g->U, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        g->U = nullptr;
+        return set_error(WL_ERR_NOMEM, "cannot allocate %zu bytes for links", bytes);
+    }
+    WL_HIP(hipMemcpyAsync(g->U, U_dev, bytes, hipMemcpyDeviceToDevice, s));
+    WL_HIP(hipStreamSynchronize(s));
+    *out = g.release();
+    return WL_OK;
+}
+
+void wl_gauge_destroy(wl_gauge U)
+{
+    if (!U) return;
+    (void)hipDeviceSynchronize();
+    drop_sets_of(U);
+    delete U;
+}
+
+wl_status wilson_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double kappa, int32_t parity,
+                        int32_t dagger, wl_prec prec, int32_t recon, void *stream)
+{
+    clear_error();
+    WL_TRY(check_gauge(U));
+    if (nrhs < 1) return set_error(WL_ERR_ARG, "nrhs = %d must be >= 1", nrhs);
+    if (parity < -1 || parity > 1) return set_error(WL_ERR_ARG, "parity must be -1, 0 or 1");
+    if (dagger != 0 && dagger != 1) return set_error(WL_ERR_ARG, "dagger must be 0 or 1");
+    if (!std::isfinite(kappa)) return set_error(WL_ERR_ARG, "kappa must be finite");
+    if (!prec_recon_ok(prec, recon)) return set_error(WL_ERR_PREC, "unsupported precision %d / recon %d", prec, recon);
+    WL_TRY(check_field(in, U, nrhs, "in"));
+    WL_TRY(check_field(out, U, nrhs, "out"));
+    const size_t bytes = (size_t)nrhs * 2 * U->geom.Vh * 24 * sizeof(double);
+    if ((const char *)in < (const char *)out + bytes && (const char *)out < (const char *)in + bytes)
+        return set_error(WL_ERR_ARG, "in and out overlap");
+    hipStream_t s = (hipStream_t)stream;
+    ExecSet *S = nullptr;
+    WL_TRY(get_set({SysEntry{U, nrhs, kappa}}, &S));
+    Field fi[2], fo[2];
+    for (int p = 0; p < 2; ++p) {
+        WL_TRY(S->field("dsl_in" + std::to_string(p), prec, &fi[p]));
+        WL_TRY(S->field("dsl_out" + std::to_string(p), prec, &fo[p]));
+    }
+    const double *cin[1] = {in};
+    double *cout[1] = {out};
+    Epi e;
+    if (parity >= 0) {
+        WL_TRY(coef_table(*S, {0, 0, 0, 0, 1.0}, &e.coef));
+        WL_TRY(pack(*S, cin, 1 - parity, fi[1 - parity], s));
+        WL_TRY(hop(*S, prec, recon, dagger, parity, fo[parity], fi[1 - parity], e, no_red(), s));
+        WL_TRY(unpack(*S, cout, parity, fo[parity], s));
+        WL_TRY(zero_canon(*S, cout, 1 - parity, s));
+    } else {
+        WL_TRY(coef_table(*S, {1.0, 0, 0, 0, -kappa}, &e.coef));
+        e.nx = 1;
+        for (int p = 0; p < 2; ++p) WL_TRY(pack(*S, cin, p, fi[p], s));
+        for (int p = 0; p < 2; ++p) {
+            e.X[0] = fi[p];
+            WL_TRY(hop(*S, prec, recon, dagger, p, fo[p], fi[1 - p], e, no_red(), s));
+        }
+        for (int p = 0; p < 2; ++p) WL_TRY(unpack(*S, cout, p, fo[p], s));
+    }
+    return WL_OK;
+}
+
+double wl_hop_bytes_per_site(wl_prec prec, int32_t recon, int32_t nrhs)
+{
+    if (!prec_recon_ok(prec, recon) || nrhs < 1) return 0.0;
+    return 8.0 * link_bytes(prec, recon) / nrhs + 2.0 * spinor_site_bytes(prec);
+}
+
+wl_status wl_prof_enable(int32_t on)
+{
+    clear_error();
+    Prof &P = prof();
+    P.on = on != 0;
+    return WL_OK;
+}
+
+wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes)
+{
+    clear_error();
+    prof_collect();
+    Prof &P = prof();
+    if (hop_launches) *hop_launches = P.launches;
+    if (hop_ms) *hop_ms = P.ms;
+    if (hop_gbytes) *hop_gbytes = P.gbytes;
+    P.launches = 0;
+    P.ms = 0.0;
+    P.gbytes = 0.0;
+    return WL_OK;
+}
+
+wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs, int32_t parity, int32_t nsets,
+                          int32_t reps, double *seconds_per_call, void *stream)
+{
+    clear_error();
+    WL_TRY(check_gauge(U));
+    if (!seconds_per_call) return set_error(WL_ERR_ARG, "null result pointer");
+    if (nrhs < 1 || nsets < 1 || nsets > 16 || reps < 1 || parity < 0 || parity > 1)
+        return set_error(WL_ERR_ARG, "nrhs >= 1, 1 <= nsets <= 16, reps >= 1, parity 0/1 required");
+    if (!prec_recon_ok(prec, recon)) return set_error(WL_ERR_PREC, "unsupported precision %d / recon %d", prec, recon);
+    hipStream_t s = (hipStream_t)stream;
+    ExecSet *S = nullptr;
+    WL_TRY(get_set({SysEntry{U, nrhs, 0.1}}, &S));
+    const SysDesc *sys0 = nullptr;
+    WL_TRY(S->sys_table(prec, recon, s, &sys0));
+    const void *links0 = nullptr;
+    WL_TRY(gauge_packed(U, prec, recon, s, &links0));
+    const size_t lbytes = (size_t)2 * 4 * link_nchunks(prec, recon) * U->geom.gstride * link_chunk_bytes(prec, recon);
+    // independent operand sets: copies of the links, fresh in/out fields
+    std::vector<void *> lcopy(nsets, nullptr);
+    std::vector<SysDesc *> dsys(nsets, nullptr);
+    std::vector<Field> fin(nsets), fout(nsets);
+    wl_status st = WL_OK;
+    for (int k = 0; k < nsets && st == WL_OK; ++k) {
+        st = S->field("bench_in" + std::to_string(k), prec, &fin[k]);
+        if (st == WL_OK) st = S->field("bench_out" + std::to_string(k), prec, &fout[k]);
+        if (st == WL_OK) st = blas(*S, BL_FILL, prec, &fin[k], 1, nullptr, no_red(), s, false);
+        if (st != WL_OK) break;
+        SysDesc h = U->geom;
+        if (k == 0) {
+            h.gauge = links0;
+        } else {
+            if (hipMalloc(&lcopy[k], lbytes) != hipSuccess) {
+                (void)hipGetLastError();
+                st = set_error(WL_ERR_NOMEM, "cannot allocate link copy");
+                break;
+            }
+            if (hipMemcpyAsync(lcopy[k], links0, lbytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+                st = set_error(WL_ERR_HIP, "link copy failed");
+                break;
+            }
+            h.gauge = lcopy[k];
+        }
+        if (hipMalloc((void **)&dsys[k], sizeof(SysDesc)) != hipSuccess ||
+            hipMemcpy(dsys[k], &h, sizeof(SysDesc), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            st = set_error(WL_ERR_NOMEM, "cannot allocate descriptor");
+            break;
+        }
+    }
+    const double *coef = nullptr;
+    if (st == WL_OK) st = coef_table(*S, {0, 0, 0, 0, 1.0}, &coef);
+    int B = 256;
+    const Layout *L = nullptr;
+    if (st == WL_OK) {
+        // tune on set 0 with the same launch the timed loop makes
+        Epi e;
+        e.coef = coef;
+        st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
+        const std::string key = "hop/" + std::to_string(prec) + "/" + std::to_string(recon) + "/0/" +
+                                std::to_string(S->nvec) + ":" + std::to_string(S->total_sites);
+        B = tuned_block(key, {64, 128, 256, 512}, s, [](int) { return hipSuccess; });
+        if (st == WL_OK) st = S->layout(B, &L);
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == WL_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        st = set_error(WL_ERR_HIP, "event creation failed");
+    if (st == WL_OK) {
+        auto launch = [&](int k) {
+            HopArgs a{};
+            a.sys = dsys[k];
+            a.vec = L->d_vec;
+            a.map = L->d_map;
+            a.active = nullptr;
+            a.nblocks = L->nblocks;
+            a.parity = parity;
+            a.in = fin[k].p;
+            a.in_norm = fin[k].n;
+            a.out = fout[k].p;
+            a.out_norm = fout[k].n;
+            a.epi.coef = coef;
+            a.red = no_red();
+            return launch_hop(prec, recon, false, a, B, s);
+        };
+        for (int k = 0; k < nsets && st == WL_OK; ++k)
+            if (launch(k) != hipSuccess) st = set_error(WL_ERR_HIP, "hop launch failed");
+        if (st == WL_OK && hipEventRecord(e0, s) != hipSuccess) st = set_error(WL_ERR_HIP, "event record failed");
+        for (int r = 0; r < reps && st == WL_OK; ++r)
+            if (launch(r % nsets) != hipSuccess) st = set_error(WL_ERR_HIP, "hop launch failed");
+        float ms = 0.f;
+        if (st == WL_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st = set_error(WL_ERR_HIP, "event timing failed");
+        if (st == WL_OK) *seconds_per_call = ms * 1e-3 / reps;
+    }
+    (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (int k = 0; k < nsets; ++k) {
+        (void)hipFree(lcopy[k]);
+        (void)hipFree(dsys[k]);
+    }
+    return st;
+}
+
+wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, void *stream)
+{
+    clear_error();
+    if (bytes < 1024 || reps < 1 || !seconds_per_call) return set_error(WL_ERR_ARG, "bytes >= 1024, reps >= 1");
+    bytes &= ~(int64_t)15;
+    hipStream_t s = (hipStream_t)stream;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(a);
+        return set_error(WL_ERR_NOMEM, "cannot allocate copy buffers");
+    }
+    wl_status st = WL_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMemsetAsync(a, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        st = set_error(WL_ERR_HIP, "setup failed");
+    if (st == WL_OK && launch_copy_bw(a, b, bytes, s) != hipSuccess) st = set_error(WL_ERR_HIP, "copy launch failed");
+    if (st == WL_OK) (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && st == WL_OK; ++r)
+        if (launch_copy_bw((r & 1) ? b : a, (r & 1) ? a : b, bytes, s) != hipSuccess)
+            st = set_error(WL_ERR_HIP, "copy launch failed");
+    float ms = 0.f;
+    if (st == WL_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = set_error(WL_ERR_HIP, "event timing failed");
+    if (st == WL_OK) *seconds_per_call = ms * 1e-3 / reps;
+    (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    return st;
+}
+
+}  // extern "C"

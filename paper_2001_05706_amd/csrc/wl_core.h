@@ -1,0 +1,530 @@
+// wl_core.h -- storage formats, packed loads/stores and the per-site Wilson
+// hopping term for gfx950.
+//
+// Everything here is __host__ __device__ so that the same arithmetic can be
+// exercised by a host build in the tests; the GPU kernels in *.hip include it.
+//
+// Packed layouts (structure of arrays, one parity per field):
+//   A "vector" is one right-hand side of one system on the Vh = V/2 sites of
+//   one parity, checkerboard index cb = s >> 1 (s the lexicographic site).
+//   Its 24 reals are split into 16-byte (or 8-byte) chunks; chunk c of site cb
+//   lives at  base[(site_off * NCHUNK) + c * stride + cb]  in units of the
+//   chunk type, so that consecutive lanes (sites) read consecutive chunks.
+//   FP64: 12 x double2          (one complex per chunk)
+//   FP32:  6 x float4           (two complex per chunk)
+//   FP16 / BF16: 3 x uint4      (four complex per chunk, value / site norm)
+//                + one float norm per site (max |v| over the 24 reals)
+//   Links of one system: [parity][mu][chunk][stride] with
+//   FP64 recon-18: 9 x double2, FP64 recon-12: 6 x double2,
+//   FP32 recon-18: 9 x float2,  FP32 recon-12: 3 x float4,
+//   FP16 / BF16 recon-12: 3 x uint2 (two complex per chunk, no norm: |U_ij| <= 1).
+//   Recon-12 keeps rows 0 and 1; row 2 = conj(row0 x row1), exact for SU(3).
+//
+// Spin-colour order of the 24 reals: v[2*(3*spin + colour) + {0: re, 1: im}],
+// DeGrand-Rossi gamma basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WL_HD __host__ __device__ __forceinline__
+
+namespace wl {
+
+enum { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+
+// ------------------------------------------------------------------ complex
+
+template <class T>
+struct cpx {
+    T re, im;
+};
+
+template <class T> WL_HD cpx<T> cmul(cpx<T> a, cpx<T> b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// conj(a) * b
+template <class T> WL_HD cpx<T> cjmul(cpx<T> a, cpx<T> b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
+template <class T> WL_HD cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> WL_HD cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+// a + i b, a - i b
+template <class T> WL_HD cpx<T> cadd_i(cpx<T> a, cpx<T> b) { return {a.re - b.im, a.im + b.re}; }
+template <class T> WL_HD cpx<T> csub_i(cpx<T> a, cpx<T> b) { return {a.re + b.im, a.im - b.re}; }
+
+// ------------------------------------------------------------------ half / bf16
+
+WL_HD float bf16_to_float(uint16_t h)
+{
+    union { uint32_t u; float f; } c;
+    c.u = (uint32_t)h << 16;
+    return c.f;
+}
+
+// round to nearest even (inputs are finite and |x| <= 1 here)
+WL_HD uint16_t float_to_bf16(float f)
+{
+    union { uint32_t u; float f; } c;
+    c.f = f;
+    uint32_t u = c.u;
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+WL_HD float f16_to_float(uint16_t h)
+{
+    union { uint16_t u; _Float16 f; } c;
+    c.u = h;
+    return (float)c.f;
+}
+
+WL_HD uint16_t float_to_f16(float f)
+{
+    union { uint16_t u; _Float16 f; } c;
+    c.f = (_Float16)f;  // round to nearest even
+    return c.u;
+}
+
+template <int P> WL_HD float lo16_to_float(uint32_t w)
+{
+    return P == P_F16 ? f16_to_float((uint16_t)(w & 0xFFFFu)) : bf16_to_float((uint16_t)(w & 0xFFFFu));
+}
+template <int P> WL_HD float hi16_to_float(uint32_t w)
+{
+    return P == P_F16 ? f16_to_float((uint16_t)(w >> 16)) : bf16_to_float((uint16_t)(w >> 16));
+}
+template <int P> WL_HD uint32_t pack2(float lo, float hi)
+{
+    uint32_t a = P == P_F16 ? float_to_f16(lo) : float_to_bf16(lo);
+    uint32_t b = P == P_F16 ? float_to_f16(hi) : float_to_bf16(hi);
+    return a | (b << 16);
+}
+
+// ------------------------------------------------------------------ storage traits
+
+template <int P> struct SpinorFmt;
+template <> struct SpinorFmt<P_F64> {
+    using real = double;
+    using chunk = double2;
+    static constexpr int nchunk = 12;
+    static constexpr bool has_norm = false;
+    static constexpr int site_bytes = 192;
+};
+template <> struct SpinorFmt<P_F32> {
+    using real = float;
+    using chunk = float4;
+    static constexpr int nchunk = 6;
+    static constexpr bool has_norm = false;
+    static constexpr int site_bytes = 96;
+};
+template <> struct SpinorFmt<P_F16> {
+    using real = float;
+    using chunk = uint4;
+    static constexpr int nchunk = 3;
+    static constexpr bool has_norm = true;
+    static constexpr int site_bytes = 52;  // 48 + 4-byte norm
+};
+template <> struct SpinorFmt<P_BF16> : SpinorFmt<P_F16> {};
+
+template <int P, int R> struct LinkFmt;
+template <> struct LinkFmt<P_F64, 18> { using chunk = double2; static constexpr int nchunk = 9; static constexpr int bytes = 144; };
+template <> struct LinkFmt<P_F64, 12> { using chunk = double2; static constexpr int nchunk = 6; static constexpr int bytes = 96; };
+template <> struct LinkFmt<P_F32, 18> { using chunk = float2; static constexpr int nchunk = 9; static constexpr int bytes = 72; };
+template <> struct LinkFmt<P_F32, 12> { using chunk = float4; static constexpr int nchunk = 3; static constexpr int bytes = 48; };
+template <> struct LinkFmt<P_F16, 12> { using chunk = uint2; static constexpr int nchunk = 3; static constexpr int bytes = 24; };
+template <> struct LinkFmt<P_BF16, 12> { using chunk = uint2; static constexpr int nchunk = 3; static constexpr int bytes = 24; };
+
+// ------------------------------------------------------------------ memory access
+
+// loads of streamed-once data (links) with the non-temporal hint, through
+// native clang vector types (the HIP vector structs are not accepted by the builtin)
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t nt_u2 __attribute__((ext_vector_type(2)));
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define WL_NT_LOAD(VT, p) __builtin_nontemporal_load((const VT *)(p))
+#else
+#define WL_NT_LOAD(VT, p) (*(const VT *)(p))
+#endif
+
+WL_HD double2 ld_stream(const double2 *p)
+{
+    const nt_d2 v = WL_NT_LOAD(nt_d2, p);
+    return double2{v.x, v.y};
+}
+WL_HD float2 ld_stream(const float2 *p)
+{
+    const nt_f2 v = WL_NT_LOAD(nt_f2, p);
+    return float2{v.x, v.y};
+}
+WL_HD float4 ld_stream(const float4 *p)
+{
+    const nt_f4 v = WL_NT_LOAD(nt_f4, p);
+    return float4{v.x, v.y, v.z, v.w};
+}
+WL_HD uint2 ld_stream(const uint2 *p)
+{
+    const nt_u2 v = WL_NT_LOAD(nt_u2, p);
+    return uint2{v.x, v.y};
+}
+
+// Element `cb` of chunk row `c`: a uniform row base (scalar registers) plus a
+// 32-bit lane offset, so each load costs one vector register of address.
+template <class CH> WL_HD const CH *row_elem(const void *base, int c, int stride, int cb)
+{
+    const char *row = (const char *)base + (size_t)c * (size_t)stride * sizeof(CH);
+    return (const CH *)(row + (uint32_t)((uint32_t)cb * (uint32_t)sizeof(CH)));
+}
+template <class CH> WL_HD CH *row_elem(void *base, int c, int stride, int cb)
+{
+    char *row = (char *)base + (size_t)c * (size_t)stride * sizeof(CH);
+    return (CH *)(row + (uint32_t)((uint32_t)cb * (uint32_t)sizeof(CH)));
+}
+
+// 24 reals of one site of one vector.  base points at chunk 0 of the vector.
+template <int P>
+WL_HD void load_spinor(const void *base, const float *norm, int stride, int cb,
+                       typename SpinorFmt<P>::real v[24])
+{
+    using F = SpinorFmt<P>;
+    using CH = typename F::chunk;
+    if constexpr (P == P_F64) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            double2 w = *row_elem<CH>(base, c, stride, cb);
+            v[2 * c] = w.x;
+            v[2 * c + 1] = w.y;
+        }
+    } else if constexpr (P == P_F32) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float4 w = *row_elem<CH>(base, c, stride, cb);
+            v[4 * c] = w.x;
+            v[4 * c + 1] = w.y;
+            v[4 * c + 2] = w.z;
+            v[4 * c + 3] = w.w;
+        }
+    } else {
+        const float nrm = *row_elem<float>(norm, 0, 0, cb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uint4 w = *row_elem<CH>(base, c, stride, cb);
+            uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[8 * c + 2 * k] = lo16_to_float<P>(q[k]) * nrm;
+                v[8 * c + 2 * k + 1] = hi16_to_float<P>(q[k]) * nrm;
+            }
+        }
+    }
+}
+
+template <int P>
+WL_HD void store_spinor(void *base, float *norm, int stride, int cb, const typename SpinorFmt<P>::real v[24])
+{
+    using F = SpinorFmt<P>;
+    typename F::chunk *b = (typename F::chunk *)base;
+    if constexpr (P == P_F64) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) *row_elem<double2>(b, c, stride, cb) = double2{v[2 * c], v[2 * c + 1]};
+    } else if constexpr (P == P_F32) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            *row_elem<float4>(b, c, stride, cb) = float4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+    } else {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
+        // a zero site stores zeros and a zero norm (point sources are zero almost everywhere)
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        *row_elem<float>(norm, 0, 0, cb) = m;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uint32_t q[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = pack2<P>(v[8 * c + 2 * k] * inv, v[8 * c + 2 * k + 1] * inv);
+            *row_elem<uint4>(b, c, stride, cb) = uint4{q[0], q[1], q[2], q[3]};
+        }
+    }
+}
+
+// One link as a 3x3 complex matrix.  base points at chunk 0 of the (parity, mu) block.
+template <int P, int R, class T>
+WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
+{
+    using F = LinkFmt<P, R>;
+    const typename F::chunk *b = (const typename F::chunk *)base;
+    if constexpr (P == P_F64) {
+#pragma unroll
+        for (int k = 0; k < (R == 18 ? 9 : 6); ++k) {
+            double2 w = ld_stream(row_elem<double2>(base, k, stride, cb));
+            u[k / 3][k % 3] = cpx<T>{(T)w.x, (T)w.y};
+        }
+    } else if constexpr (P == P_F32 && R == 18) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            float2 w = ld_stream(row_elem<float2>(base, k, stride, cb));
+            u[k / 3][k % 3] = cpx<T>{(T)w.x, (T)w.y};
+        }
+    } else if constexpr (P == P_F32) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float4 w = ld_stream(row_elem<float4>(base, c, stride, cb));
+            const int k = 2 * c;
+            u[k / 3][k % 3] = cpx<T>{(T)w.x, (T)w.y};
+            u[(k + 1) / 3][(k + 1) % 3] = cpx<T>{(T)w.z, (T)w.w};
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uint2 w = ld_stream(row_elem<uint2>(base, c, stride, cb));
+            const int k = 2 * c;
+            u[k / 3][k % 3] = cpx<T>{(T)lo16_to_float<P>(w.x), (T)hi16_to_float<P>(w.x)};
+            u[(k + 1) / 3][(k + 1) % 3] = cpx<T>{(T)lo16_to_float<P>(w.y), (T)hi16_to_float<P>(w.y)};
+        }
+    }
+    if constexpr (R == 12) {
+        // row2 = conj(row0 x row1)
+        u[2][0] = {u[0][1].re * u[1][2].re - u[0][1].im * u[1][2].im - (u[0][2].re * u[1][1].re - u[0][2].im * u[1][1].im),
+                   -(u[0][1].re * u[1][2].im + u[0][1].im * u[1][2].re - (u[0][2].re * u[1][1].im + u[0][2].im * u[1][1].re))};
+        u[2][1] = {u[0][2].re * u[1][0].re - u[0][2].im * u[1][0].im - (u[0][0].re * u[1][2].re - u[0][0].im * u[1][2].im),
+                   -(u[0][2].re * u[1][0].im + u[0][2].im * u[1][0].re - (u[0][0].re * u[1][2].im + u[0][0].im * u[1][2].re))};
+        u[2][2] = {u[0][0].re * u[1][1].re - u[0][0].im * u[1][1].im - (u[0][1].re * u[1][0].re - u[0][1].im * u[1][0].im),
+                   -(u[0][0].re * u[1][1].im + u[0][0].im * u[1][1].re - (u[0][1].re * u[1][0].im + u[0][1].im * u[1][0].re))};
+    }
+}
+
+template <int P, int R>
+WL_HD void store_link(void *base, int stride, int cb, const double u[18] /* row-major complex */)
+{
+    using F = LinkFmt<P, R>;
+    typename F::chunk *b = (typename F::chunk *)base;
+    if constexpr (P == P_F64) {
+        for (int k = 0; k < (R == 18 ? 9 : 6); ++k) b[(size_t)k * stride + cb] = double2{u[2 * k], u[2 * k + 1]};
+    } else if constexpr (P == P_F32 && R == 18) {
+        for (int k = 0; k < 9; ++k) b[(size_t)k * stride + cb] = float2{(float)u[2 * k], (float)u[2 * k + 1]};
+    } else if constexpr (P == P_F32) {
+        for (int c = 0; c < 3; ++c)
+            b[(size_t)c * stride + cb] = float4{(float)u[4 * c], (float)u[4 * c + 1], (float)u[4 * c + 2], (float)u[4 * c + 3]};
+    } else {
+        for (int c = 0; c < 3; ++c)
+            b[(size_t)c * stride + cb] = uint2{pack2<P>((float)u[4 * c], (float)u[4 * c + 1]),
+                                               pack2<P>((float)u[4 * c + 2], (float)u[4 * c + 3])};
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+
+// Per-system lattice description (lives in device memory; read with scalar loads).
+struct SysDesc {
+    int32_t L[4];
+    int32_t Lxh;         // Lx / 2
+    int32_t Vh;          // sites per parity
+    int32_t stride;      // chunk stride of one vector (>= Vh, multiple of 64)
+    int32_t tap;         // 1: antiperiodic in t
+    int32_t gstride;     // chunk stride of the packed links (== stride)
+    int32_t pad_;
+    const void *gauge;   // packed links of the precision used by the launch
+};
+
+// site coordinates from checkerboard index and parity
+struct Site {
+    int x, y, z, t;
+};
+
+WL_HD Site cb_coords(const SysDesc &d, int cb, int parity)
+{
+    Site s;
+    int xh = cb % d.Lxh;
+    int r = cb / d.Lxh;
+    s.y = r % d.L[1];
+    r /= d.L[1];
+    s.z = r % d.L[2];
+    s.t = r / d.L[2];
+    s.x = 2 * xh + ((s.y + s.z + s.t + parity) & 1);
+    return s;
+}
+
+// ------------------------------------------------------------------ half-spinor algebra
+//
+// For P = 1 + sg * gamma_mu (sg = -1 forward hop of H, +1 backward; swapped for
+// H^dagger) the 4-spinor P psi is fixed by two spin components h0, h1:
+//   mu=x: h0 = p0 + sg i p3, h1 = p1 + sg i p2;   rows 2,3 = -sg i h1, -sg i h0
+//   mu=y: h0 = p0 - sg p3,   h1 = p1 + sg p2;     rows 2,3 =  sg h1,  -sg h0
+//   mu=z: h0 = p0 + sg i p2, h1 = p1 - sg i p3;   rows 2,3 = -sg i h0,  sg i h1
+//   mu=t: h0 = p0 + sg p2,   h1 = p1 + sg p3;     rows 2,3 =  sg h0,   sg h1
+// (from the DeGrand-Rossi matrices; 12 flop per projection, 24 per reconstruction)
+
+template <int MU, int SG, class T>
+WL_HD void project(const T v[24], cpx<T> h0[3], cpx<T> h1[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cpx<T> p0{v[2 * (0 + c)], v[2 * (0 + c) + 1]};
+        cpx<T> p1{v[2 * (3 + c)], v[2 * (3 + c) + 1]};
+        cpx<T> p2{v[2 * (6 + c)], v[2 * (6 + c) + 1]};
+        cpx<T> p3{v[2 * (9 + c)], v[2 * (9 + c) + 1]};
+        if constexpr (MU == 0) {
+            h0[c] = SG > 0 ? cadd_i(p0, p3) : csub_i(p0, p3);
+            h1[c] = SG > 0 ? cadd_i(p1, p2) : csub_i(p1, p2);
+        } else if constexpr (MU == 1) {
+            h0[c] = SG > 0 ? csub(p0, p3) : cadd(p0, p3);
+            h1[c] = SG > 0 ? cadd(p1, p2) : csub(p1, p2);
+        } else if constexpr (MU == 2) {
+            h0[c] = SG > 0 ? cadd_i(p0, p2) : csub_i(p0, p2);
+            h1[c] = SG > 0 ? csub_i(p1, p3) : cadd_i(p1, p3);
+        } else {
+            h0[c] = SG > 0 ? cadd(p0, p2) : csub(p0, p2);
+            h1[c] = SG > 0 ? cadd(p1, p3) : csub(p1, p3);
+        }
+    }
+}
+
+// acc += P psi given U h0, U h1 (already multiplied by the link)
+template <int MU, int SG, class T>
+WL_HD void reconstruct_add(T acc[24], const cpx<T> g0[3], const cpx<T> g1[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[2 * (0 + c)] += g0[c].re;
+        acc[2 * (0 + c) + 1] += g0[c].im;
+        acc[2 * (3 + c)] += g1[c].re;
+        acc[2 * (3 + c) + 1] += g1[c].im;
+        cpx<T> r2, r3;
+        if constexpr (MU == 0) {
+            // -sg i h1, -sg i h0 ; i(a+ib) = -b + ia
+            r2 = SG > 0 ? cpx<T>{g1[c].im, -g1[c].re} : cpx<T>{-g1[c].im, g1[c].re};
+            r3 = SG > 0 ? cpx<T>{g0[c].im, -g0[c].re} : cpx<T>{-g0[c].im, g0[c].re};
+        } else if constexpr (MU == 1) {
+            r2 = SG > 0 ? g1[c] : cpx<T>{-g1[c].re, -g1[c].im};
+            r3 = SG > 0 ? cpx<T>{-g0[c].re, -g0[c].im} : g0[c];
+        } else if constexpr (MU == 2) {
+            r2 = SG > 0 ? cpx<T>{g0[c].im, -g0[c].re} : cpx<T>{-g0[c].im, g0[c].re};
+            r3 = SG > 0 ? cpx<T>{-g1[c].im, g1[c].re} : cpx<T>{g1[c].im, -g1[c].re};
+        } else {
+            r2 = SG > 0 ? g0[c] : cpx<T>{-g0[c].re, -g0[c].im};
+            r3 = SG > 0 ? g1[c] : cpx<T>{-g1[c].re, -g1[c].im};
+        }
+        acc[2 * (6 + c)] += r2.re;
+        acc[2 * (6 + c) + 1] += r2.im;
+        acc[2 * (9 + c)] += r3.re;
+        acc[2 * (9 + c) + 1] += r3.im;
+    }
+}
+
+// g = U h (ADJ = false) or U^dagger h (ADJ = true)
+template <bool ADJ, class T>
+WL_HD void su3_mul(const cpx<T> u[3][3], const cpx<T> h[3], cpx<T> g[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cpx<T> s{0, 0};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if constexpr (ADJ) {
+                cpx<T> p = cjmul(u[b][a], h[b]);
+                s.re += p.re;
+                s.im += p.im;
+            } else {
+                cpx<T> p = cmul(u[a][b], h[b]);
+                s.re += p.re;
+                s.im += p.im;
+            }
+        }
+        g[a] = s;
+    }
+}
+
+// Everything the per-site hop needs.
+struct HopSite {
+    const void *in;       // input vector (opposite parity), chunk 0
+    const float *in_norm; // FP16/BF16 norms of the input vector
+    int stride;           // chunk stride of spinor vectors
+    const void *gauge;    // packed links of the system: [parity][mu][chunk][gstride]
+    int gstride;
+};
+
+template <int SP, int GP, int R, int MU, int DIR, bool DAG, class T>
+WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s, int cb, T acc[24])
+{
+    // neighbour coordinates and boundary factor
+    int nx = s.x, ny = s.y, nz = s.z, nt = s.t;
+    bool flip = false;
+    if constexpr (MU == 0) nx = DIR > 0 ? (s.x + 1 == d.L[0] ? 0 : s.x + 1) : (s.x == 0 ? d.L[0] - 1 : s.x - 1);
+    if constexpr (MU == 1) ny = DIR > 0 ? (s.y + 1 == d.L[1] ? 0 : s.y + 1) : (s.y == 0 ? d.L[1] - 1 : s.y - 1);
+    if constexpr (MU == 2) nz = DIR > 0 ? (s.z + 1 == d.L[2] ? 0 : s.z + 1) : (s.z == 0 ? d.L[2] - 1 : s.z - 1);
+    if constexpr (MU == 3) {
+        if (DIR > 0) {
+            flip = (s.t + 1 == d.L[3]) && d.tap;
+            nt = s.t + 1 == d.L[3] ? 0 : s.t + 1;
+        } else {
+            flip = (s.t == 0) && d.tap;
+            nt = s.t == 0 ? d.L[3] - 1 : s.t - 1;
+        }
+    }
+    const int ncb = (nx >> 1) + d.Lxh * (ny + d.L[1] * (nz + d.L[2] * nt));
+
+    T v[24];
+    load_spinor<SP>(a.in, a.in_norm, a.stride, ncb, v);
+    // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
+    constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
+    cpx<T> h0[3], h1[3];
+    project<MU, SG>(v, h0, h1);
+    if (flip) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = {-h0[c].re, -h0[c].im};
+            h1[c] = {-h1[c].re, -h1[c].im};
+        }
+    }
+    // forward: U_mu(x) on this parity; backward: U_mu(x - mu)^dagger on the other parity
+    constexpr int NCH = LinkFmt<GP, R>::nchunk;
+    const int lpar = DIR > 0 ? parity : 1 - parity;
+    const int lcb = DIR > 0 ? cb : ncb;
+    const char *lbase = (const char *)a.gauge +
+                        (size_t)((lpar * 4 + MU) * NCH) * a.gstride * sizeof(typename LinkFmt<GP, R>::chunk);
+    cpx<T> u[3][3];
+    load_link<GP, R, T>(lbase, a.gstride, lcb, u);
+    cpx<T> g0[3], g1[3];
+    su3_mul<(DIR < 0), T>(u, h0, g0);
+    su3_mul<(DIR < 0), T>(u, h1, g1);
+    reconstruct_add<MU, SG>(acc, g0, g1);
+}
+
+// Keeps the compiler from hoisting the loads of later directions above this
+// point: one direction pair's operands in flight per wave bounds the register
+// footprint, and occupancy supplies the memory-level parallelism.
+// The accumulator is passed through the fence as register operands so that the
+// arithmetic of earlier directions completes before it (otherwise the loaded
+// operands of every direction stay live until a combined tail).
+template <class T> WL_HD void sched_fence(T acc[24])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+    for (int k = 0; k < 24; ++k) asm volatile("" : "+v"(acc[k]));
+    asm volatile("" ::: "memory");
+#endif
+}
+#define WL_SCHED_FENCE() sched_fence(acc)
+
+// acc = (H psi)(x) (or H^dagger) at output site cb of `parity`; psi is read on the other parity.
+template <int SP, int GP, int R, bool DAG, class T>
+WL_HD void hop_site(const SysDesc &d, const HopSite &a, int parity, int cb, T acc[24])
+{
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = 0;
+    const Site s = cb_coords(d, cb, parity);
+    hop_dir<SP, GP, R, 0, +1, DAG>(d, a, parity, s, cb, acc);
+    hop_dir<SP, GP, R, 0, -1, DAG>(d, a, parity, s, cb, acc);
+    WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 1, +1, DAG>(d, a, parity, s, cb, acc);
+    hop_dir<SP, GP, R, 1, -1, DAG>(d, a, parity, s, cb, acc);
+    WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 2, +1, DAG>(d, a, parity, s, cb, acc);
+    hop_dir<SP, GP, R, 2, -1, DAG>(d, a, parity, s, cb, acc);
+    WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 3, +1, DAG>(d, a, parity, s, cb, acc);
+    hop_dir<SP, GP, R, 3, -1, DAG>(d, a, parity, s, cb, acc);
+    WL_SCHED_FENCE();
+}
+
+}  // namespace wl

@@ -1,0 +1,181 @@
+// wl_host.h -- host-side runtime of the library: errors, gauge handles,
+// execution sets (systems x right-hand sides with device-resident tables),
+// fields, the launch autotuner and the kernel timer.
+#pragma once
+
+#include <functional>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/wilson.h"
+#include "wl_kernels.h"
+
+namespace wl {
+
+// ------------------------------------------------------------------ errors
+
+wl_status set_error(wl_status s, const char *fmt, ...);
+void clear_error();
+
+#define WL_HIP(call)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return ::wl::set_error(WL_ERR_HIP, "%s: %s (%s:%d)", #call,       \
+                                                     hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+#define WL_TRY(expr)                      \
+    do {                                  \
+        wl_status s_ = (expr);            \
+        if (s_ != WL_OK) return s_;       \
+    } while (0)
+
+// true if [p, p + bytes) lies inside one device allocation
+bool device_range_ok(const void *p, size_t bytes);
+
+// ------------------------------------------------------------------ precision helpers
+
+int spinor_site_bytes(int prec);  // bytes per site of a packed vector (incl. norm)
+int chunk_bytes(int prec);
+int nchunks(int prec);
+bool prec_recon_ok(int prec, int recon);
+int link_bytes(int prec, int recon);
+constexpr int kStrideAlign = 64;
+inline int padded(int vh) { return (vh + kStrideAlign - 1) / kStrideAlign * kStrideAlign; }
+
+}  // namespace wl
+
+// ------------------------------------------------------------------ gauge handle
+
+struct wl_gauge_s {
+    wl::SysDesc geom;          // gauge pointer unset
+    int device = 0;
+    double *U = nullptr;       // canonical FP64 copy (device)
+    void *packed[4][2] = {};   // [prec][recon == 12]
+    ~wl_gauge_s();
+};
+
+namespace wl {
+
+wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const void **out);
+
+// ------------------------------------------------------------------ execution sets
+
+struct Field {
+    void *p = nullptr;
+    float *n = nullptr;  // FP16/BF16 norms
+    int prec = -1;
+};
+
+struct Layout {
+    int B = 0;
+    int nblocks = 0;
+    int npslots = 0;
+    VecDesc *d_vec = nullptr;
+    BlkMap *d_map = nullptr;
+};
+
+struct SysEntry {
+    wl_gauge g;
+    int nrhs;
+    double kappa;
+};
+
+// A set of systems (each a gauge handle with nrhs right-hand sides) whose
+// vectors share every field and every launch.
+class ExecSet {
+public:
+    ExecSet(const std::vector<SysEntry> &systems);
+    ~ExecSet();
+    wl_status init();
+
+    std::vector<SysEntry> systems;
+    std::vector<VecDesc> vec;  // nblk / pslot0 filled per layout
+    int nvec = 0;
+    size_t total_sites = 0;    // sum of strides over vectors
+
+    // device tables
+    wl_status sys_table(int prec, int recon, hipStream_t s, const SysDesc **out);
+    wl_status layout(int B, const Layout **out);
+    int32_t *d_active = nullptr;
+    std::vector<int32_t> h_active;
+    wl_status upload_active(hipStream_t s);
+
+    // reduction state (per vector unless noted)
+    double *partials = nullptr;  // max slots over layouts (B = 64)
+    uint32_t *counters = nullptr;
+    double *sc = nullptr;        // scalar arena, see SC_* below
+    int32_t *bad = nullptr;
+    double *hist = nullptr;      // residual history: [kHist][nvec]
+    double *h_pinned = nullptr;  // pinned host mirror of hist, scalars and flags
+    static constexpr int kHist = 64;
+
+    enum { SC_ALPHA = 0, SC_BETA, SC_GAM, SC_QQ, SC_RR, SC_ETA, SC_TMP, SC_N };
+    double *scal(int which) { return sc + (size_t)which * nvec; }
+
+    // fields by name, allocated on first use
+    wl_status field(const std::string &name, int prec, Field *out);
+
+    std::map<std::pair<int, int>, SysDesc *> d_sys;
+    std::map<int, Layout> layouts;
+    std::map<std::string, Field> fields;
+    std::map<std::vector<double>, double *> coefs;
+    std::map<std::string, hipGraphExec_t> graphs;  // captured iteration chunks
+    int max_pslots = 0;
+};
+
+// Find or build the cached set for these systems (fields persist between calls).
+wl_status get_set(const std::vector<SysEntry> &systems, ExecSet **out);
+void drop_sets_of(wl_gauge g);
+
+// ------------------------------------------------------------------ launches on a set
+
+struct Epi {
+    int nx = 0;
+    int g5 = 0;
+    const double *coef = nullptr;  // device [nsys][5]
+    Field X[4];
+};
+
+RedSpec no_red();
+RedSpec red_spec(ExecSet &S, int kind, double *dst);
+
+// out_p = epilogue(hop(in_{1-p})) on every active vector of the set
+wl_status hop(ExecSet &S, int prec, int recon, bool dag, int out_parity, const Field &out, const Field &in,
+              const Epi &e, const RedSpec &red, hipStream_t s, bool use_active = true);
+wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
+               hipStream_t s, bool use_active = true);
+wl_status convert(ExecSet &S, const Field &dst, const Field &src, hipStream_t s, bool use_active = true);
+// canonical <-> packed for one parity; canon[i] is the canonical field array of system i
+wl_status pack(ExecSet &S, const double *const *canon, int parity, const Field &f, hipStream_t s);
+wl_status unpack(ExecSet &S, double *const *canon, int parity, const Field &f, hipStream_t s);
+wl_status zero_canon(ExecSet &S, double *const *canon, int parity, hipStream_t s);
+
+// device coefficient tables [nsys][5], cached by content
+wl_status coef_table(ExecSet &S, const std::vector<double> &c, const double **out);
+
+// ------------------------------------------------------------------ tuning and timing
+
+int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream_t s,
+                const std::function<hipError_t(int)> &run);
+bool capturing(hipStream_t s);
+
+struct Prof {
+    bool on = false;
+    int64_t launches = 0;
+    double ms = 0.0;
+    double gbytes = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<double> pending_bytes;
+};
+Prof &prof();
+void prof_collect();
+
+// algorithmic bytes of one hop on all active vectors of the set
+double hop_bytes(const ExecSet &S, int prec, int recon, bool use_active);
+double blas_bytes(const ExecSet &S, int prec, int passes, bool use_active);
+extern thread_local double g_bytes_acc;  // running algorithmic-byte counter of the current call
+
+}  // namespace wl

@@ -1,0 +1,60 @@
+// wl_kernels.h -- host-side launchers of the device kernels.
+#pragma once
+
+#include "wl_launch.h"
+
+namespace wl {
+
+struct BlasArgs {
+    const SysDesc *sys;
+    const VecDesc *vec;
+    const BlkMap *map;
+    const int32_t *active;
+    int32_t nblocks;
+    int32_t pad_;
+    void *f[4];
+    float *fn[4];
+    const double *s0;  // per-vector scalar (alpha or beta)
+    RedSpec red;
+};
+
+constexpr int kMaxSys = 64;  // systems per set (canonical pointers travel by value)
+
+struct PackArgs {
+    const SysDesc *sys;
+    const VecDesc *vec;
+    const BlkMap *map;
+    int32_t nblocks;
+    int32_t parity;
+    void *f;
+    float *fn;
+    const double *canon[kMaxSys];  // per system: canonical fields of all its rhs
+};
+
+// hop.hip
+hipError_t launch_hop(int prec, int recon, bool dag, const HopArgs &a, int block, hipStream_t s);
+
+// blas.hip -- all operate on the vectors of one set through its block map
+enum BlasOp {
+    BL_CG_UPDATE = 0,  // x += alpha p; r -= alpha q; |r|^2          f = {x, p, r, q}, s0 = alpha
+    BL_XPAY = 1,       // p = s + beta p                             f = {p, s},       s0 = beta
+    BL_ACCUM = 2,      // y(F64) += x; x = 0                         f = {y, x}
+    BL_NORM2 = 3,      // |x|^2                                      f = {x}
+    BL_ZERO = 4,       // x = 0                                      f = {x}
+    BL_COPY = 5,       // y = x                                      f = {y, x}
+    BL_FILL = 6,       // x = deterministic pattern (benchmark operands)  f = {x}
+    BL_SCALE_RSQRT = 7,// x *= 1/sqrt(s0[v])                         f = {x}
+};
+hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
+// y (prec_dst) = x (prec_src), f = {y, x}
+hipError_t launch_convert(int prec_dst, int prec_src, const BlasArgs &a, int block, hipStream_t s);
+
+// pack.hip
+hipError_t launch_pack_spinor(int prec, const PackArgs &a, int block, hipStream_t s);
+hipError_t launch_unpack_spinor(int prec, const PackArgs &a, int block, hipStream_t s);
+hipError_t launch_zero_canon(const PackArgs &a, int block, hipStream_t s);
+hipError_t launch_pack_gauge(int prec, int recon, const double *U_canon, void *out, const SysDesc &d,
+                             hipStream_t s);
+hipError_t launch_copy_bw(const void *in, void *out, size_t bytes, hipStream_t s);
+
+}  // namespace wl

@@ -1,0 +1,149 @@
+"""GPU solves of the Wilson system (even-odd CGNR, mixed precision with FP64
+reliable updates, batched) through the C ABI, checked against the FP64 oracle.
+
+For every solve the true residual |eta - D psi| / |eta| is recomputed by the
+oracle's whole-lattice operator from the GPU solution (independent of the
+GPU's own report), and the solution is compared with the oracle's solution:
+|psi - psi_oracle| / |psi_oracle| <= 2 cond(D) tol.
+"""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+import oracle
+from tests.gpu_util import from_dev, need_gpu, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def true_resid(L, U, eta, psi, kappa):
+    r = eta - oracle.wilson(L, U, psi, kappa)
+    return np.linalg.norm(r.reshape(r.shape[0], -1), axis=1) / np.linalg.norm(eta.reshape(eta.shape[0], -1), axis=1)
+
+
+def solve(w, L, U, eta, kappa, tol, sloppy, recon=12, delta=0.1, maxiter=2000, check=True, x0=None):
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta) if x0 is None else x0)
+    st, info = w.wilson_cg(g, to_dev(eta), x, eta.shape[0], kappa, tol, maxiter, sloppy, recon, delta, check=check)
+    out = from_dev(x, eta.shape)
+    g.close()
+    return st, info, out
+
+
+def test_config1_plain_fp64_4x4():
+    """4^4 Haar links, kappa 0.12, Gaussian source, FP64 throughout, tol 1e-12."""
+    w = need_gpu()
+    L = (4, 4, 4, 4)
+    U = li.haar_links(L, 1001)
+    eta = li.gaussian_spinor(L, 2001)
+    st, info, x = solve(w, L, U, eta, 0.12, 1e-12, "f64", 18)
+    ref, conv, it, _ = oracle.cg_eo(L, U, eta, 0.12, 1e-12)
+    tr = true_resid(L, U, eta, x, 0.12)
+    assert info[0]["converged"] and tr[0] <= 1e-12
+    assert abs(info[0]["true_resid"] - tr[0]) <= 1e-13
+    assert rel(x, ref) <= 2 * 4.0 * 1e-12  # cond(D) = 3.96 for this configuration
+    assert abs(info[0]["iters"] - it[0]) <= 6
+
+
+@pytest.mark.parametrize("sloppy,recon", [("f32", 12), ("f32", 18), ("f16", 12), ("bf16", 12), ("f64", 12)])
+def test_mixed_precision_reaches_1e10(sloppy, recon):
+    w = need_gpu()
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2002, nrhs=2)
+    st, info, x = solve(w, L, U, eta, 0.1245, 1e-10, sloppy, recon)
+    tr = true_resid(L, U, eta, x, 0.1245)
+    ref, _, _, _ = oracle.cg_eo(L, U, eta, 0.1245, 1e-12)
+    for r in range(2):
+        assert info[r]["converged"] and tr[r] <= 1e-10, (sloppy, info[r], tr[r])
+        assert abs(info[r]["true_resid"] - tr[r]) <= 1e-3 * tr[r] + 1e-15
+        assert info[r]["reliable_updates"] >= 1
+    assert rel(x, ref) <= 2 * 20 * 1e-10
+
+
+def test_point_sources_twelve_rhs():
+    """The 12 spin-colour point sources at the origin, solved together."""
+    w = need_gpu()
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1004)
+    eta = li.point_sources(L)
+    st, info, x = solve(w, L, U, eta, 0.1245, 1e-10, "f32")
+    tr = true_resid(L, U, eta, x, 0.1245)
+    assert np.all(tr <= 1e-10) and all(i["converged"] for i in info)
+    # the solution of one source alone agrees with the batched one
+    st1, info1, x1 = solve(w, L, U, eta[5:6], 0.1245, 1e-10, "f32")
+    assert rel(x1[0], x[5]) <= 1e-9
+
+
+def test_uneven_batch_multi():
+    """Lattices of different sizes, kappas and RHS counts in one batched solve."""
+    w = need_gpu()
+    specs = [((4, 4, 4, 4), 0.12, 2), ((6, 6, 6, 6), 0.1245, 1), ((4, 4, 4, 8), 0.124, 3), ((8, 8, 8, 4), 0.1245, 1)]
+    gs, etas, xs, Us = [], [], [], []
+    for i, (L, k, n) in enumerate(specs):
+        U = li.near_identity_links(L, 0.3, 3000 + i)
+        Us.append(U)
+        gs.append(w.Gauge(L, to_dev(U)))
+        e = li.gaussian_spinor(L, 4000 + i, nrhs=n)
+        etas.append(e)
+        xs.append(to_dev(np.zeros_like(e)))
+    st, info = w.wilson_cg_multi(gs, [to_dev(e) for e in etas], xs, [s[2] for s in specs], [s[1] for s in specs],
+                                 1e-10, 2000, "f32", 12, 0.1)
+    j = 0
+    for i, (L, k, n) in enumerate(specs):
+        x = from_dev(xs[i], etas[i].shape)
+        tr = true_resid(L, Us[i], etas[i], x, k)
+        assert np.all(tr <= 1e-10), (i, tr)
+        for r in range(n):
+            assert info[j]["converged"]
+            j += 1
+    for g in gs:
+        g.close()
+
+
+def test_solver_edge_cases():
+    w = need_gpu()
+    L = (4, 4, 4, 4)
+    U = li.haar_links(L, 1001)
+    eta = li.gaussian_spinor(L, 2001, nrhs=2)
+    eta[1] = 0.0  # a zero source gives x = 0, converged
+    st, info, x = solve(w, L, U, eta, 0.12, 1e-10, "f32", x0=np.ones_like(eta))
+    assert info[1]["converged"] and info[1]["iters"] == 0 and np.abs(x[1]).max() == 0.0
+    assert info[0]["converged"]
+    # a converged guess needs no iterations
+    st, info2, x2 = solve(w, L, U, eta[:1], 0.12, 1e-10, "f32", x0=x[:1])
+    assert info2[0]["converged"] and info2[0]["iters"] == 0
+    # maxiter too small: NOCONV with info filled and the iterate returned
+    st, info3, x3 = solve(w, L, U, eta[:1], 0.12, 1e-12, "f32", maxiter=2, check=False)
+    assert st == w.WL_ERR_NOCONV and info3[0]["converged"] == 0 and info3[0]["iters"] >= 2
+    assert 0 < info3[0]["true_resid"] < 1
+    # a NaN in the source is reported, not iterated
+    bad = eta[:1].copy()
+    bad[0, 7, 1, 2] = np.nan
+    st, info4, _ = solve(w, L, U, bad, 0.12, 1e-10, "f32", check=False)
+    assert st == w.WL_ERR_NONFINITE
+    # invalid arguments
+    g = w.Gauge(L, to_dev(U))
+    d = to_dev(eta[:1])
+    for args in [(1, -0.1, 1e-10, 10), (1, 0.12, 0.0, 10), (1, 0.12, 1e-10, 0), (0, 0.12, 1e-10, 10)]:
+        st, _ = w.wilson_cg(g, d, to_dev(eta[:1]), *args, check=False)
+        assert st == w.WL_ERR_ARG
+    st, _ = w.wilson_cg(g, d, to_dev(eta[:1]), 1, 0.12, 1e-10, 10, "f32", 12, 1.5, check=False)
+    assert st == w.WL_ERR_ARG
+    g.close()
+
+
+def test_config2_size_fp32_and_fp64():
+    """24^3 x 48, eps = 0.3, kappa = 0.1245, tol 1e-10: plain FP64 and mixed FP32."""
+    w = need_gpu()
+    L = (24, 24, 24, 48)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2002)
+    res = {}
+    for sloppy, recon in [("f64", 18), ("f32", 12), ("f16", 12)]:
+        st, info, x = solve(w, L, U, eta, 0.1245, 1e-10, sloppy, recon, delta=0.1)
+        tr = true_resid(L, U, eta, x, 0.1245)
+        assert info[0]["converged"] and tr[0] <= 1e-10, (sloppy, info, tr)
+        res[sloppy] = x
+    assert rel(res["f32"], res["f64"]) <= 1e-8
+    assert rel(res["f16"], res["f64"]) <= 1e-8

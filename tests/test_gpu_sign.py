@@ -1,0 +1,59 @@
+"""GPU Chebyshev sign function of the overlap kernel and GPU power iteration,
+through the C ABI, against the FP64 oracle (same polynomial, same scale)."""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+import oracle
+from tests.gpu_util import from_dev, need_gpu, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_power_iteration_matches_oracle():
+    w = need_gpu()
+    L = (4, 4, 4, 8)
+    U = li.near_identity_links(L, 0.2, 1005)
+    v0 = li.gaussian_spinor(L, 7)
+    g = w.Gauge(L, to_dev(U))
+    got = w.wl_hw2_lmax(g, 1.5, to_dev(v0), 50)
+    ref = oracle.hw2_lmax(L, U, 1.5, v0[0], iters=50)
+    assert abs(got - ref) / ref <= 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("prec,recon,gate", [("f64", 18, 1e-12), ("f32", 12, 1e-5), ("f32", 18, 1e-5)])
+def test_sign_matches_oracle(prec, recon, gate):
+    w = need_gpu()
+    L = (4, 4, 4, 8)
+    U = li.near_identity_links(L, 0.2, 1005)
+    psi = li.gaussian_spinor(L, 2005, nrhs=3)
+    scale = 1.02 * oracle.hw2_lmax(L, U, 1.5, psi[0], iters=200)
+    lo, hi, deg = 0.003, 1.0, 200
+    ref = oracle.sign_cheb(L, U, psi, 1.5, deg, lo, hi, scale)
+    g = w.Gauge(L, to_dev(U))
+    out = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, to_dev(psi), out, 3, 1.5, deg, lo, hi, scale, prec, recon)
+    got = from_dev(out, psi.shape)
+    assert rel(got, ref) <= gate, rel(got, ref)
+    # eps^2 = 1 on the GPU result, to the precision of the arithmetic
+    out2 = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, to_dev(got), out2, 3, 1.5, deg, lo, hi, scale, prec, recon)
+    assert rel(from_dev(out2, psi.shape), psi) <= (1e-9 if prec == "f64" else 1e-4)
+    g.close()
+
+
+def test_sign_automatic_scale():
+    """scale <= 0: the library estimates lambda_max itself; the sign is unchanged."""
+    w = need_gpu()
+    L = (4, 4, 4, 4)
+    U = li.near_identity_links(L, 0.2, 1006)
+    psi = li.gaussian_spinor(L, 2006)
+    g = w.Gauge(L, to_dev(U))
+    out = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, to_dev(psi), out, 1, 1.5, 200, 0.003, 1.0, -1.0, "f64", 18)
+    got = from_dev(out, psi.shape)
+    out2 = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, to_dev(got), out2, 1, 1.5, 200, 0.003, 1.0, -1.0, "f64", 18)
+    assert rel(from_dev(out2, psi.shape), psi) <= 1e-8
+    g.close()
