@@ -19,6 +19,8 @@
 // |eta - D psi| / |eta| is computed in FP64 with the whole-lattice operator.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "wl_host.h"
@@ -144,6 +146,8 @@ struct Cg {
         const std::string key = "cg/" + std::to_string(k) + "/" + std::to_string(sloppy) + "/" + std::to_string(recon);
         auto it = S.graphs.find(key);
         if (it == S.graphs.end()) {
+            const SysDesc *tab = nullptr;  // packed links and tables exist before capture
+            WL_TRY(S.sys_table(sloppy, recon, s, &tab));
             hipStream_t cs = capture_stream();
             if (!cs) return set_error(WL_ERR_HIP, "cannot create the capture stream");
             const double saved = g_bytes_acc;
@@ -201,6 +205,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
     cg.sloppy = sloppy;
     const char *ge = getenv("WL_GRAPHS");
     cg.use_graphs = !(ge && ge[0] == '0');
+    const bool trace = getenv("WL_DEBUG") != nullptr;  // per-chunk solver trace on stderr
     WL_TRY(cg.setup());
     const int nv = S.nvec;
     double *hp = S.h_pinned;  // [kHist * nv] history, then scalars
@@ -272,6 +277,14 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
             int32_t *hbad = (int32_t *)(hp + (size_t)ExecSet::kHist * nv);
             WL_HIP(hipMemcpyAsync(hbad, S.bad, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, s));
             WL_HIP(hipStreamSynchronize(s));
+            if (trace) {
+                double sc[ExecSet::SC_N];
+                for (int j = 0; j < ExecSet::SC_N; ++j)
+                    WL_HIP(hipMemcpy(&sc[j], S.scal(j), sizeof(double), hipMemcpyDeviceToHost));
+                fprintf(stderr, "[wl cg] chunk k=%d prec=%d rhs0: |r| %.3e -> %.3e  alpha %.3e beta %.3e gamma %.3e bad %d\n",
+                        k, cg.sloppy, std::sqrt(hp[0]), std::sqrt(hp[(size_t)(k - 1) * nv]), sc[ExecSet::SC_ALPHA],
+                        sc[ExecSet::SC_BETA], sc[ExecSet::SC_GAM], (int)hbad[0]);
+            }
             std::vector<int> upd(nv, 0);
             bool anyupd = false;
             double rate = 0.0;
@@ -314,6 +327,9 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 for (int v = 0; v < nv; ++v) {
                     if (!upd[v]) continue;
                     const double r = std::sqrt(hp[v]);
+                    if (trace)
+                        fprintf(stderr, "[wl cg] update rhs %d after %d iters: FP64 |r|/|eta| = %.3e (prev %.3e)\n", v,
+                                iters[v], r / eta_n[v], last_true[v] / eta_n[v]);
                     ++updates[v];
                     if (!std::isfinite(r)) {
                         status = set_error(WL_ERR_NONFINITE, "non-finite FP64 residual (rhs %d)", v);
@@ -347,6 +363,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                             stall[v] = 0;
                         }
                     ++escalations;
+                    if (trace) fprintf(stderr, "[wl cg] stagnation: sloppy precision raised to %d\n", cg.sloppy);
                 }
                 for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v] && !done[v];
                 WL_TRY(S.upload_active(s));

@@ -13,13 +13,19 @@
 
 namespace wl {
 
-// Occupancy target per storage precision: the hop is bound by memory latency
-// and bandwidth, so the register budget is capped to keep enough waves in
-// flight (FP32/FP16/BF16: 4 waves per SIMD, i.e. <= 128 VGPRs; FP64: 3).
-template <int SP> struct HopOcc { static constexpr int waves = SP == P_F64 ? 3 : 4; };
+// Launch variants the autotuner chooses from, with the block size:
+//   fence: directions whose operands may be in flight together per wave
+//   waves: occupancy target (waves per SIMD), which caps registers at 512/waves
+//   nt:    non-temporal link loads (links used once) or cached (shared by RHS)
+template <int SP, int VAR> struct HopVar {
+    static constexpr int fence = VAR == 0 || VAR == 3 ? 2 : 1;
+    static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR == 3 ? 3 : 4) : (VAR == 0 || VAR == 3 ? 4 : VAR == 1 ? 5 : 6);
+    static constexpr bool nt = VAR != 3;
+};
+constexpr int kHopVariants = 4;
 
-template <int SP, int GP, int R, bool DAG>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopOcc<SP>::waves))) void k_hop(HopArgs a)
+template <int SP, int GP, int R, bool DAG, int VAR>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves))) void k_hop(HopArgs a)
 {
     using T = typename SpinorFmt<SP>::real;
     using CH = typename SpinorFmt<SP>::chunk;
@@ -42,7 +48,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopOcc<SP>:
         hs.gauge = sd.gauge;
         hs.gstride = sd.gstride;
         T acc[24];
-        hop_site<SP, GP, R, DAG>(sd, hs, a.parity, cb, acc);
+        hop_site<SP, GP, R, DAG, HopVar<SP, VAR>::fence, HopVar<SP, VAR>::nt>(sd, hs, a.parity, cb, acc);
 
         const double *cf = a.epi.coef + vd.sys * 5;
         const T c = (T)cf[4];
@@ -76,24 +82,38 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopOcc<SP>:
     if (a.red.kind != RED_NONE) block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
 }
 
-template <int SP, int GP, int R>
-static hipError_t launch_hop_t(bool dag, const HopArgs &a, int block, hipStream_t s)
+template <int SP, int GP, int R, int VAR>
+static hipError_t launch_hop_v(bool dag, const HopArgs &a, int block, hipStream_t s)
 {
     if (dag)
-        hipLaunchKernelGGL((k_hop<SP, GP, R, true>), dim3(a.nblocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_hop<SP, GP, R, true, VAR>), dim3(a.nblocks), dim3(block), 0, s, a);
     else
-        hipLaunchKernelGGL((k_hop<SP, GP, R, false>), dim3(a.nblocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_hop<SP, GP, R, false, VAR>), dim3(a.nblocks), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_hop(int prec, int recon, bool dag, const HopArgs &a, int block, hipStream_t s)
+template <int SP, int GP, int R>
+static hipError_t launch_hop_t(int var, bool dag, const HopArgs &a, int block, hipStream_t s)
 {
-    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(dag, a, block, s);
-    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(dag, a, block, s);
-    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(dag, a, block, s);
-    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(dag, a, block, s);
-    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(dag, a, block, s);
-    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(dag, a, block, s);
+    switch (var) {
+    case 0: return launch_hop_v<SP, GP, R, 0>(dag, a, block, s);
+    case 1: return launch_hop_v<SP, GP, R, 1>(dag, a, block, s);
+    case 2: return launch_hop_v<SP, GP, R, 2>(dag, a, block, s);
+    case 3: return launch_hop_v<SP, GP, R, 3>(dag, a, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int hop_variants() { return kHopVariants; }
+
+hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s)
+{
+    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(var, dag, a, block, s);
+    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(var, dag, a, block, s);
+    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(var, dag, a, block, s);
+    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(var, dag, a, block, s);
+    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(var, dag, a, block, s);
+    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(var, dag, a, block, s);
     return hipErrorInvalidValue;
 }
 

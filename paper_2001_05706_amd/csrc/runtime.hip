@@ -168,6 +168,7 @@ int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (getenv("WL_DEBUG")) fprintf(stderr, "[wl tune] %s -> %d (%.4f ms / 3 launches)\n", key.c_str(), best, best_ms);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;
     return best;
@@ -192,6 +193,8 @@ wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const voi
 {
     if (!prec_recon_ok(prec, recon)) return set_error(WL_ERR_PREC, "unsupported precision %d / recon %d", prec, recon);
     void *&p = g->packed[prec][recon == 12 ? 1 : 0];
+    if (!p && capturing(s))  // packing would record a memset node into the caller's graph
+        return set_error(WL_ERR_HIP, "links of precision %d / recon %d first needed inside a graph capture", prec, recon);
     if (!p) {
         const size_t bytes = (size_t)2 * 4 * link_nchunks(prec, recon) * g->geom.gstride * link_chunk_bytes(prec, recon);
         if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -480,6 +483,21 @@ static std::string set_sig(const ExecSet &S)
     return std::to_string(S.nvec) + ":" + std::to_string(S.total_sites);
 }
 
+std::string hop_key(const ExecSet &S, int prec, int recon, bool dag)
+{
+    return "hop/" + std::to_string(prec) + "/" + std::to_string(recon) + "/" + std::to_string((int)dag) + "/" +
+           set_sig(S);
+}
+
+// (variant, block size) pairs encoded as variant * 1024 + block
+std::vector<int> hop_candidates()
+{
+    std::vector<int> c;
+    for (int v = 0; v < hop_variants(); ++v)
+        for (int b : {64, 128, 256, 512}) c.push_back(v * 1024 + b);
+    return c;
+}
+
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
               const RedSpec &red, hipStream_t s, bool use_active)
 {
@@ -507,13 +525,13 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         a.red = rs;
         return a;
     };
-    const std::string key = "hop/" + std::to_string(prec) + "/" + std::to_string(recon) + "/" + std::to_string(dag) +
-                            "/" + set_sig(S);
-    const int B = tuned_block(key, {64, 128, 256, 512}, s, [&](int b) -> hipError_t {
+    const std::string key = hop_key(S, prec, recon, dag);
+    const int cfg = tuned_block(key, hop_candidates(), s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;
-        if (S.layout(b, &L) != WL_OK) return hipErrorOutOfMemory;
-        return launch_hop(prec, recon, dag, mk(L, no_red()), b, s);
+        if (S.layout(c % 1024, &L) != WL_OK) return hipErrorOutOfMemory;
+        return launch_hop(prec, recon, dag, c / 1024, mk(L, no_red()), c % 1024, s);
     });
+    const int B = cfg % 1024, var = cfg / 1024;
     const Layout *L = nullptr;
     WL_TRY(S.layout(B, &L));
     const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active);
@@ -526,7 +544,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         WL_HIP(hipEventCreate(&e1));
         WL_HIP(hipEventRecord(e0, s));
     }
-    WL_HIP(launch_hop(prec, recon, dag, mk(L, red), B, s));
+    WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
     if (timed) {
         WL_HIP(hipEventRecord(e1, s));
         P.pending.push_back({e0, e1});
@@ -845,16 +863,15 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
     }
     const double *coef = nullptr;
     if (st == WL_OK) st = coef_table(*S, {0, 0, 0, 0, 1.0}, &coef);
-    int B = 256;
+    int B = 256, cfg = 256;
     const Layout *L = nullptr;
     if (st == WL_OK) {
         // tune on set 0 with the same launch the timed loop makes
         Epi e;
         e.coef = coef;
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
-        const std::string key = "hop/" + std::to_string(prec) + "/" + std::to_string(recon) + "/0/" +
-                                std::to_string(S->nvec) + ":" + std::to_string(S->total_sites);
-        B = tuned_block(key, {64, 128, 256, 512}, s, [](int) { return hipSuccess; });
+        cfg = tuned_block(hop_key(*S, prec, recon, false), hop_candidates(), s, [](int) { return hipSuccess; });
+        B = cfg % 1024;
         if (st == WL_OK) st = S->layout(B, &L);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -875,7 +892,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
             a.out_norm = fout[k].n;
             a.epi.coef = coef;
             a.red = no_red();
-            return launch_hop(prec, recon, false, a, B, s);
+            return launch_hop(prec, recon, false, cfg / 1024, a, B, s);
         };
         for (int k = 0; k < nsets && st == WL_OK; ++k)
             if (launch(k) != hipSuccess) st = set_error(WL_ERR_HIP, "hop launch failed");

@@ -248,7 +248,17 @@ WL_HD void store_spinor(void *base, float *norm, int stride, int cb, const typen
 }
 
 // One link as a 3x3 complex matrix.  base points at chunk 0 of the (parity, mu) block.
-template <int P, int R, class T>
+// Link element load: non-temporal (NT) when each link is used once per launch,
+// plain when other right-hand sides of the launch re-read it from L2.
+template <bool NT, class CH> WL_HD CH ld_link(const CH *p)
+{
+    if constexpr (NT)
+        return ld_stream(p);
+    else
+        return *p;
+}
+
+template <int P, int R, class T, bool NT = true>
 WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
 {
     using F = LinkFmt<P, R>;
@@ -256,19 +266,19 @@ WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
     if constexpr (P == P_F64) {
 #pragma unroll
         for (int k = 0; k < (R == 18 ? 9 : 6); ++k) {
-            double2 w = ld_stream(row_elem<double2>(base, k, stride, cb));
+            double2 w = ld_link<NT>(row_elem<double2>(base, k, stride, cb));
             u[k / 3][k % 3] = cpx<T>{(T)w.x, (T)w.y};
         }
     } else if constexpr (P == P_F32 && R == 18) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            float2 w = ld_stream(row_elem<float2>(base, k, stride, cb));
+            float2 w = ld_link<NT>(row_elem<float2>(base, k, stride, cb));
             u[k / 3][k % 3] = cpx<T>{(T)w.x, (T)w.y};
         }
     } else if constexpr (P == P_F32) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float4 w = ld_stream(row_elem<float4>(base, c, stride, cb));
+            float4 w = ld_link<NT>(row_elem<float4>(base, c, stride, cb));
             const int k = 2 * c;
             u[k / 3][k % 3] = cpx<T>{(T)w.x, (T)w.y};
             u[(k + 1) / 3][(k + 1) % 3] = cpx<T>{(T)w.z, (T)w.w};
@@ -276,7 +286,7 @@ WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            uint2 w = ld_stream(row_elem<uint2>(base, c, stride, cb));
+            uint2 w = ld_link<NT>(row_elem<uint2>(base, c, stride, cb));
             const int k = 2 * c;
             u[k / 3][k % 3] = cpx<T>{(T)lo16_to_float<P>(w.x), (T)hi16_to_float<P>(w.x)};
             u[(k + 1) / 3][(k + 1) % 3] = cpx<T>{(T)lo16_to_float<P>(w.y), (T)hi16_to_float<P>(w.y)};
@@ -443,7 +453,7 @@ struct HopSite {
     int gstride;
 };
 
-template <int SP, int GP, int R, int MU, int DIR, bool DAG, class T>
+template <int SP, int GP, int R, int MU, int DIR, bool DAG, bool NT, class T>
 WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s, int cb, T acc[24])
 {
     // neighbour coordinates and boundary factor
@@ -483,7 +493,7 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
     const char *lbase = (const char *)a.gauge +
                         (size_t)((lpar * 4 + MU) * NCH) * a.gstride * sizeof(typename LinkFmt<GP, R>::chunk);
     cpx<T> u[3][3];
-    load_link<GP, R, T>(lbase, a.gstride, lcb, u);
+    load_link<GP, R, T, NT>(lbase, a.gstride, lcb, u);
     cpx<T> g0[3], g1[3];
     su3_mul<(DIR < 0), T>(u, h0, g0);
     su3_mul<(DIR < 0), T>(u, h1, g1);
@@ -506,24 +516,30 @@ template <class T> WL_HD void sched_fence(T acc[24])
 }
 #define WL_SCHED_FENCE() sched_fence(acc)
 
-// acc = (H psi)(x) (or H^dagger) at output site cb of `parity`; psi is read on the other parity.
-template <int SP, int GP, int R, bool DAG, class T>
+// acc = (H psi)(x) (or H^dagger) at output site cb of `parity`; psi is read on
+// the other parity.  FENCE = number of directions whose operands may be in
+// flight together (1, 2 or 8); NT = non-temporal link loads.
+template <int SP, int GP, int R, bool DAG, int FENCE = 2, bool NT = true, class T>
 WL_HD void hop_site(const SysDesc &d, const HopSite &a, int parity, int cb, T acc[24])
 {
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
     const Site s = cb_coords(d, cb, parity);
-    hop_dir<SP, GP, R, 0, +1, DAG>(d, a, parity, s, cb, acc);
-    hop_dir<SP, GP, R, 0, -1, DAG>(d, a, parity, s, cb, acc);
-    WL_SCHED_FENCE();
-    hop_dir<SP, GP, R, 1, +1, DAG>(d, a, parity, s, cb, acc);
-    hop_dir<SP, GP, R, 1, -1, DAG>(d, a, parity, s, cb, acc);
-    WL_SCHED_FENCE();
-    hop_dir<SP, GP, R, 2, +1, DAG>(d, a, parity, s, cb, acc);
-    hop_dir<SP, GP, R, 2, -1, DAG>(d, a, parity, s, cb, acc);
-    WL_SCHED_FENCE();
-    hop_dir<SP, GP, R, 3, +1, DAG>(d, a, parity, s, cb, acc);
-    hop_dir<SP, GP, R, 3, -1, DAG>(d, a, parity, s, cb, acc);
+    hop_dir<SP, GP, R, 0, +1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE == 1) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 0, -1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE <= 2) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 1, +1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE == 1) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 1, -1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE <= 2) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 2, +1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE == 1) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 2, -1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE <= 2) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 3, +1, DAG, NT>(d, a, parity, s, cb, acc);
+    if constexpr (FENCE == 1) WL_SCHED_FENCE();
+    hop_dir<SP, GP, R, 3, -1, DAG, NT>(d, a, parity, s, cb, acc);
     WL_SCHED_FENCE();
 }
 

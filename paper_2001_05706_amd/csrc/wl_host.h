@@ -161,6 +161,8 @@ wl_status coef_table(ExecSet &S, const std::vector<double> &c, const double **ou
 int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream_t s,
                 const std::function<hipError_t(int)> &run);
 bool capturing(hipStream_t s);
+std::string hop_key(const ExecSet &S, int prec, int recon, bool dag);
+std::vector<int> hop_candidates();
 
 struct Prof {
     bool on = false;

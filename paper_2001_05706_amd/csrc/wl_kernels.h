@@ -32,7 +32,9 @@ struct PackArgs {
 };
 
 // hop.hip
-hipError_t launch_hop(int prec, int recon, bool dag, const HopArgs &a, int block, hipStream_t s);
+// var selects a launch variant (0 .. hop_variants()-1, see hop.hip)
+hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s);
+int hop_variants();
 
 // blas.hip -- all operate on the vectors of one set through its block map
 enum BlasOp {
