@@ -43,6 +43,146 @@ def cg_iteration_bytes(w, prec, recon, vh):
     return vh * (4 * w.wl_hop_bytes_per_site(prec, recon, 1) + 2 * site + 6 * site + 3 * site)
 
 
+def _guard(fn):
+    try:
+        return fn()
+    except Exception as e:  # a failed side measurement is reported, not fatal
+        log("side measurement failed: %r" % (e,))
+        return {"error": repr(e)}
+
+
+def _timed(torch, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    best, res = 1e30, None
+    for _ in range(reps):
+        t = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best, res
+
+
+def _dev(torch, a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.float64)).to(dev)
+
+
+def bench_batch12(w, torch, li, dev, a):
+    """12 spin-colour point sources on 24^3 x 48: one batched solve vs 12 single solves."""
+    L = (24, 24, 24, 48)
+    U = li.near_identity_links(L, 0.3, 1004)
+    eta = li.point_sources(L)
+    g = w.Gauge(L, _dev(torch, U, dev))
+    e = _dev(torch, eta, dev).reshape(-1)
+    x = torch.zeros_like(e)
+    per = e.numel() // 12
+
+    def batched():
+        x.zero_()
+        return w.wilson_cg(g, e, x, 12, 0.1245, 1e-10, 5000, "f32", 12, a.delta)[1]
+
+    def single():
+        infos = []
+        for r in range(12):
+            xr = x[r * per:(r + 1) * per]
+            xr.zero_()
+            infos += w.wilson_cg(g, e[r * per:(r + 1) * per], xr, 1, 0.1245, 1e-10, 5000, "f32", 12, a.delta)[1]
+        return infos
+
+    tb, ib = _timed(torch, batched)
+    ts, is_ = _timed(torch, single, reps=1)
+    g.close()
+    r = {"batched_ms": round(tb * 1e3, 2), "sequential_ms": round(ts * 1e3, 2),
+         "speedup": round(ts / tb, 3), "ms_per_rhs": round(tb * 1e3 / 12, 3),
+         "max_iters": max(i["iters"] for i in ib), "worst_true_resid": max(i["true_resid"] for i in ib),
+         "batched_GBs": round(ib[0]["gbytes"] / tb, 1)}
+    log("batched 12 rhs: %s" % r)
+    return r
+
+
+def bench_uneven(w, torch, li, dev, a):
+    """4 x {8^4, 12^4, 16^3x32, 24^3x48}, Gaussian sources: one batched solve vs 16 solves."""
+    sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 48)]
+    specs = [L for L in sizes for _ in range(4)]
+    gs, es, xs = [], [], []
+    for n, L in enumerate(specs):
+        gs.append(w.Gauge(L, _dev(torch, li.near_identity_links(L, 0.3, 3000 + n), dev)))
+        es.append(_dev(torch, li.gaussian_spinor(L, 4000 + n), dev))
+        xs.append(torch.zeros_like(es[-1]))
+
+    def batched():
+        for x in xs:
+            x.zero_()
+        return w.wilson_cg_multi(gs, es, xs, [1] * 16, [0.1245] * 16, 1e-10, 5000, "f32", 12, a.delta)[1]
+
+    def single():
+        out = []
+        for gg, e, x in zip(gs, es, xs):
+            x.zero_()
+            out += w.wilson_cg(gg, e, x, 1, 0.1245, 1e-10, 5000, "f32", 12, a.delta)[1]
+        return out
+
+    tb, ib = _timed(torch, batched)
+    ts, is_ = _timed(torch, single, reps=1)
+    for gg in gs:
+        gg.close()
+    r = {"batched_ms": round(tb * 1e3, 2), "sequential_ms": round(ts * 1e3, 2), "speedup": round(ts / tb, 3),
+         "sites": int(sum(np.prod(L) for L in specs)), "worst_true_resid": max(i["true_resid"] for i in ib),
+         "batched_GBs": round(ib[0]["gbytes"] / tb, 1)}
+    log("uneven batch: %s" % r)
+    return r
+
+
+def bench_mixed32(w, torch, li, dev, a):
+    """32^3 x 64, kappa 0.1248: FP16 / BF16 sloppy (recon-12) vs plain FP64."""
+    L = (32, 32, 32, 64)
+    g = w.Gauge(L, _dev(torch, li.near_identity_links(L, 0.3, 1003), dev))
+    e = _dev(torch, li.gaussian_spinor(L, 2003), dev)
+    x = torch.zeros_like(e)
+    r = {}
+    for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]:
+        def run():
+            x.zero_()
+            return w.wilson_cg(g, e, x, 1, 0.1248, 1e-10, 5000, sl, rc, a.delta)[1][0]
+        try:
+            t, inf = _timed(torch, run, reps=2)
+            r[sl] = {"ms": round(t * 1e3, 2), "iters": inf["iters"], "true_resid": inf["true_resid"],
+                     "GBs": round(inf["gbytes"] / t, 1)}
+        except w.WilsonError as ex:
+            r[sl] = {"error": str(ex)}
+        log("32^3x64 %s: %s" % (sl, r[sl]))
+    g.close()
+    if "ms" in r.get("f64", {}):
+        for sl in ("f32", "f16", "bf16"):
+            if "ms" in r.get(sl, {}):
+                r[sl]["speedup_vs_fp64"] = round(r["f64"]["ms"] / r[sl]["ms"], 3)
+    return r
+
+
+def bench_sign(w, torch, li, dev, a):
+    """Degree-200 Chebyshev sign function of H_W (rho 1.5) on 12 RHS, 16^3 x 32, FP32."""
+    L = (16, 16, 16, 32)
+    vh = int(np.prod(L)) // 2
+    g = w.Gauge(L, _dev(torch, li.near_identity_links(L, 0.2, 1005), dev))
+    v = _dev(torch, li.gaussian_spinor(L, 2005, nrhs=12), dev)
+    out = torch.zeros_like(v)
+    back = torch.zeros_like(v)
+    t, _ = _timed(torch, lambda: w.overlap_sign_cheb(g, v, out, 12, 1.5, 200, 0.003, 1.0, 42.25, "f32", 12), reps=2)
+    w.overlap_sign_cheb(g, out, back, 12, 1.5, 200, 0.003, 1.0, 42.25, "f32", 12)
+    torch.cuda.synchronize()
+    res = float(torch.linalg.norm(back - v) / torch.linalg.norm(v))
+    g.close()
+    # per Clenshaw step and RHS: two whole-lattice H_W (4 hops) with 1 + 4 epilogue
+    # reads; links shared by the 12 RHS
+    site, link = 96, 48
+    step = 2 * (2 * vh) * (8 * link / 12.0 + 2 * site) + 2 * vh * (1 + 4) * site
+    gb = 12 * 202 * step / 1e9
+    r = {"ms": round(t * 1e3, 2), "ms_per_rhs": round(t * 1e3 / 12, 3), "eps2_resid_f32": res,
+         "GBs": round(gb / t, 1), "hw_applications_per_rhs": 2 * 201 + 1}
+    log("sign function: %s" % r)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,7 +194,9 @@ def main():
     ap.add_argument("--lattice", default="24,24,24,48")
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle CG iterations timed for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the FP64 / D-slash side measurements")
+    ap.add_argument("--no-extra", action="store_true", help="skip every side measurement")
+    ap.add_argument("--extras", default="cg,dslash,batch,uneven,mixed32,sign",
+                    help="side measurements outside the timed region (comma list)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -157,7 +299,8 @@ def main():
         },
     }
 
-    if not a.no_extra:
+    extras = set() if a.no_extra else set(a.extras.split(","))
+    if "cg" in extras:
         # plain FP64 GPU solver (recon 18) and other sloppy precisions, same workload
         cmp = {}
         for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]:
@@ -180,6 +323,7 @@ def main():
         out["cg_time_to_1e-10_ms"] = cmp
         if "ms" in cmp.get("f64", {}) and "ms" in cmp.get(a.sloppy, {}):
             out["cg_speedup_vs_fp64"] = round(cmp["f64"]["ms"] / cmp[a.sloppy]["ms"], 3)
+    if "dslash" in extras:
         # stand-alone D-slash (hop only), warm and cold operand protocols
         ds = {}
         for prec, rc in [("f64", 18), ("f32", 12), ("f16", 12)]:
@@ -190,7 +334,28 @@ def main():
                 ds["%s_r%d_%s" % (prec, rc, name)] = {"us": round(sec * 1e6, 2), "GBs": round(gbs, 1),
                                                      "TFLOPs": round(1320 * vh / sec / 1e12, 3)}
                 log("dslash %s r%d %s: %.2f us, %.1f GB/s" % (prec, rc, name, sec * 1e6, gbs))
+        try:
+            g12 = w.Gauge(L, Ud)
+            sec = w.wl_bench_dslash(g12, "f32", 12, 12, 0, 1, 20, stream)
+            bps = w.wl_hop_bytes_per_site("f32", 12, 12)
+            ds["f32_r12_12rhs_warm"] = {"us": round(sec * 1e6, 2), "GBs": round(12 * bps * vh / sec / 1e9, 1),
+                                        "TFLOPs": round(12 * 1320 * vh / sec / 1e12, 3)}
+            log("dslash f32 r12 x12 rhs: %.2f us, %.1f GB/s" % (sec * 1e6, 12 * bps * vh / sec / 1e9))
+            g12.close()
+        except w.WilsonError as e:
+            ds["f32_r12_12rhs_warm"] = {"error": str(e)}
         out["dslash"] = ds
+    side = {}
+    if "batch" in extras:
+        side["batched_12_point_sources"] = _guard(lambda: bench_batch12(w, torch, li, dev, a))
+    if "uneven" in extras:
+        side["uneven_batch_16_lattices"] = _guard(lambda: bench_uneven(w, torch, li, dev, a))
+    if "mixed32" in extras:
+        side["mixed_32c64"] = _guard(lambda: bench_mixed32(w, torch, li, dev, a))
+    if "sign" in extras:
+        side["sign_function_16c32"] = _guard(lambda: bench_sign(w, torch, li, dev, a))
+    if side:
+        out["configs"] = side
 
     # bandwidth reference: a plain copy of a known size (read + write); its
     # rocprofv3 FETCH_SIZE / WRITE_SIZE readings calibrate the traffic counters

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
         store_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
         nrm = site_norm2(r);
     }
-    if (a.red.kind != RED_NONE) block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
+    if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
 template <int P>
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_norm2(BlasArgs a)
         load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
         nrm = site_norm2(x);
     }
-    block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
+    block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
 template <int P>
@@ -178,6 +178,25 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
     case BL_SCALE_RSQRT: hipLaunchKernelGGL(k_scale_rsqrt<P>, g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// One block per vector: fixed-order sum of the vector's partials, then the
+// finishing step (scalar update) of the reduction kind.
+__global__ __launch_bounds__(256) void k_red_finalize(RedSpec r, const VecDesc *vec, const int32_t *active)
+{
+    const int v = blockIdx.x;
+    if (active && !active[v]) return;
+    const VecDesc vd = vec[v];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < vd.nblk; i += blockDim.x) s += r.partials[vd.pslot0 + i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) red_finalize(r, v, s);
+}
+
+hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_red_finalize, dim3(nvec), dim3(256), 0, s, r, vec, active);
     return hipGetLastError();
 }
 

@@ -266,6 +266,25 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
         WL_TRY(blas(S, BL_COPY, cg.sloppy, cp, 2, nullptr, no_red(), s));
         int k = 4;
         bool first = true;
+        // FP16/BF16 recurrences drift faster: shorter chunks, so updates are not late
+        auto kmax = [&]() { return cg.sloppy == P_F16 || cg.sloppy == P_BF16 ? 8.0 : 32.0; };
+        auto kfrac = [&]() { return cg.sloppy == P_F16 || cg.sloppy == P_BF16 ? 0.6 : 1.0; };
+        std::vector<double> rmin(nv);
+        for (int v = 0; v < nv; ++v) rmin[v] = rmax[v];
+        // raise the sloppy precision one step; p is converted (restarted vectors overwrite it)
+        auto escalate = [&](const char *why) -> wl_status {
+            const int next = cg.sloppy == P_F32 ? P_F64 : P_F32;
+            Field p_old = cg.p;
+            cg.sloppy = next;
+            WL_TRY(cg.sloppy_fields());
+            for (int v = 0; v < nv; ++v) S.h_active[v] = !done[v];
+            WL_TRY(S.upload_active(s));
+            WL_TRY(convert(S, cg.p, p_old, s));
+            WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+            ++escalations;
+            if (trace) fprintf(stderr, "[wl cg] %s: sloppy precision raised to %d\n", why, cg.sloppy);
+            return WL_OK;
+        };
         while (true) {
             // the first chunk runs eagerly: it tunes launch shapes and builds layouts before capture
             const bool graphs = cg.use_graphs;
@@ -285,41 +304,55 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                         k, cg.sloppy, std::sqrt(hp[0]), std::sqrt(hp[(size_t)(k - 1) * nv]), sc[ExecSet::SC_ALPHA],
                         sc[ExecSet::SC_BETA], sc[ExecSet::SC_GAM], (int)hbad[0]);
             }
-            std::vector<int> upd(nv, 0);
-            bool anyupd = false;
+            std::vector<int> upd(nv, 0), restart(nv, 0);
+            bool anyupd = false, anybad = false;
             double rate = 0.0;
             int nrate = 0;
             for (int v = 0; v < nv; ++v) {
                 if (done[v]) continue;
-                if (hbad[v]) {
-                    status = set_error(WL_ERR_NONFINITE, "non-finite value in the iteration (rhs %d)", v);
-                    break;
-                }
                 iters[v] += k;
-                double rfirst = 0, rlast = 0;
+                double rfirst = 0, rlast = 0, rlow = 1e300;
+                bool bad_v = hbad[v] != 0;
                 for (int j = 0; j < k; ++j) {
                     const double r = std::sqrt(hp[(size_t)j * nv + v]);
                     if (!std::isfinite(r)) {
-                        status = set_error(WL_ERR_NONFINITE, "non-finite residual (rhs %d)", v);
+                        bad_v = true;
                         break;
                     }
                     if (j == 0) rfirst = r;
                     rlast = r;
+                    rlow = std::min(rlow, r);
                     if (r <= target[v] || r < delta * rmax[v]) upd[v] = 1;
                 }
-                if (iters[v] >= maxiter) upd[v] = 1;
-                if (rfirst > 0 && rlast > 0 && k > 1) {
-                    rate += std::log10(rfirst / rlast) / (k - 1);
-                    ++nrate;
+                if (bad_v) {
+                    // the sloppy state is lost: restart from the FP64 accumulator
+                    upd[v] = restart[v] = 1;
+                    anybad = true;
+                } else {
+                    if (rlow >= rmin[v]) upd[v] = 1;  // no progress over a whole chunk
+                    rmin[v] = std::min(rmin[v], rlow);
+                    if (rfirst > 0 && rlast > 0 && k > 1) {
+                        rate += std::log10(rfirst / rlast) / (k - 1);
+                        ++nrate;
+                    }
                 }
+                if (iters[v] >= maxiter) upd[v] = 1;
                 anyupd = anyupd || upd[v];
             }
-            if (status != WL_OK) break;
+            if (anybad && cg.sloppy == P_F64) {
+                status = set_error(WL_ERR_NONFINITE, "non-finite value in the FP64 iteration");
+                break;
+            }
             if (anyupd) {
-                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v];
+                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v] && !restart[v];
                 WL_TRY(S.upload_active(s));
                 Field ac[2] = {cg.xh, cg.xl};
                 WL_TRY(blas(S, BL_ACCUM, cg.sloppy, ac, 2, nullptr, no_red(), s));
+                for (int v = 0; v < nv; ++v) S.h_active[v] = restart[v];
+                WL_TRY(S.upload_active(s));
+                WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v];
+                WL_TRY(S.upload_active(s));
                 WL_TRY(cg.residual64());
                 WL_HIP(hipMemcpyAsync(hp, S.scal(ExecSet::SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
                 WL_HIP(hipStreamSynchronize(s));
@@ -328,8 +361,8 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     if (!upd[v]) continue;
                     const double r = std::sqrt(hp[v]);
                     if (trace)
-                        fprintf(stderr, "[wl cg] update rhs %d after %d iters: FP64 |r|/|eta| = %.3e (prev %.3e)\n", v,
-                                iters[v], r / eta_n[v], last_true[v] / eta_n[v]);
+                        fprintf(stderr, "[wl cg] update rhs %d after %d iters: FP64 |r|/|eta| = %.3e (prev %.3e)%s\n", v,
+                                iters[v], r / eta_n[v], last_true[v] / eta_n[v], restart[v] ? " restart" : "");
                     ++updates[v];
                     if (!std::isfinite(r)) {
                         status = set_error(WL_ERR_NONFINITE, "non-finite FP64 residual (rhs %d)", v);
@@ -339,36 +372,38 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                         done[v] = conv[v] = 1;
                     } else if (iters[v] >= maxiter) {
                         done[v] = 1;
-                    } else {
+                    } else if (!restart[v]) {
                         stall[v] = r > 0.5 * last_true[v] ? stall[v] + 1 : 0;
                         if (stall[v] >= 2) stalled = true;
                     }
                     last_true[v] = r;
-                    rmax[v] = r;
+                    rmax[v] = rmin[v] = r;
                 }
                 if (status != WL_OK) break;
-                if (stalled && cg.sloppy != P_F64) {
-                    // raise the sloppy precision: keep the search direction, restart the rest from FP64
-                    const int next = cg.sloppy == P_F32 ? P_F64 : P_F32;
-                    Field p_old = cg.p;
-                    cg.sloppy = next;
-                    WL_TRY(cg.sloppy_fields());
-                    for (int v = 0; v < nv; ++v) S.h_active[v] = !done[v];
-                    WL_TRY(S.upload_active(s));
-                    WL_TRY(convert(S, cg.p, p_old, s));
-                    WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+                // after the FP64 accumulation above, so no vector loses its sloppy progress
+                if ((stalled || anybad) && cg.sloppy != P_F64) {
+                    WL_TRY(escalate(anybad ? "non-finite sloppy iterate" : "stagnation"));
+                    WL_HIP(hipMemsetAsync(S.bad, 0, sizeof(int32_t) * nv, s));
                     for (int v = 0; v < nv; ++v)
                         if (!done[v]) {
                             upd[v] = 1;
                             stall[v] = 0;
                         }
-                    ++escalations;
-                    if (trace) fprintf(stderr, "[wl cg] stagnation: sloppy precision raised to %d\n", cg.sloppy);
                 }
                 for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v] && !done[v];
                 WL_TRY(S.upload_active(s));
                 WL_TRY(convert(S, cg.rl, cg.rh, s));
                 WL_TRY(cg.apply_M(cg.sloppy, recon, true, cg.sv, cg.rl, cg.tl, red_spec(S, RED_GAMMA, nullptr)));
+                bool anyrestart = false;
+                for (int v = 0; v < nv; ++v) {
+                    S.h_active[v] = restart[v] && !done[v];
+                    anyrestart = anyrestart || S.h_active[v];
+                }
+                if (anyrestart) {  // p = s: a fresh search direction
+                    WL_TRY(S.upload_active(s));
+                    Field cp[2] = {cg.p, cg.sv};
+                    WL_TRY(blas(S, BL_COPY, cg.sloppy, cp, 2, nullptr, no_red(), s));
+                }
             }
             bool left = false;
             for (int v = 0; v < nv; ++v) {
@@ -377,10 +412,12 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
             }
             if (!left) break;
             WL_TRY(S.upload_active(s));
-            // next chunk spans about one reliable-update interval
+            // next chunk spans about one reliable-update interval (less in half precision)
             if (nrate > 0 && rate / nrate > 1e-3) {
-                const double want = std::log10(1.0 / delta) / (rate / nrate);
-                k = round_chunk(std::min(32.0, std::max(2.0, want)));
+                const double want = kfrac() * std::log10(1.0 / delta) / (rate / nrate);
+                k = round_chunk(std::min(kmax(), std::max(2.0, want)));
+            } else {
+                k = round_chunk(std::min(kmax(), (double)k));
             }
         }
     }

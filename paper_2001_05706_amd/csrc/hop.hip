@@ -79,7 +79,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
         store_spinor<SP>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
         if (a.red.kind != RED_NONE) nrm = site_norm2(o);
     }
-    if (a.red.kind != RED_NONE) block_reduce_finish(a.red, bm.v, vd.nblk, vd.pslot0, bm.lblk, nrm);
+    if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
 template <int SP, int GP, int R, int VAR>

@@ -545,6 +545,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         WL_HIP(hipEventRecord(e0, s));
     }
     WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
+    if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, use_active ? S.d_active : nullptr, S.nvec, s));
     if (timed) {
         WL_HIP(hipEventRecord(e1, s));
         P.pending.push_back({e0, e1});
@@ -580,6 +581,7 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     else
         g_bytes_acc += blas_bytes(S, prec, passes[op], use_active);
     WL_HIP(launch_blas(op, prec, a, kBlasBlock, s));
+    if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, a.active, S.nvec, s));
     return WL_OK;
 }
 

@@ -48,6 +48,8 @@ enum BlasOp {
     BL_SCALE_RSQRT = 7,// x *= 1/sqrt(s0[v])                         f = {x}
 };
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
+// fixed-order sum of each active vector's block partials and the reduction's finishing step
+hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s);
 // y (prec_dst) = x (prec_src), f = {y, x}
 hipError_t launch_convert(int prec_dst, int prec_src, const BlasArgs &a, int block, hipStream_t s);
 

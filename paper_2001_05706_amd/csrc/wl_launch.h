@@ -38,8 +38,8 @@ WL_HD int xcd_remap(int h, int nb)
     return k * q + (k < r ? k : r) + i;
 }
 
-// Reduction of a per-site scalar to one FP64 number per vector, then a
-// finishing step executed by the last block of that vector.
+// Reduction of a per-site scalar to one FP64 number per vector (block partials,
+// then a fixed-order finishing pass), and the finishing step applied to it.
 enum RedKind {
     RED_NONE = 0,
     RED_STORE = 1,   // dst[v] = sum
@@ -53,7 +53,7 @@ struct RedSpec {
     int32_t kind;
     int32_t pad_;
     double *partials;    // per (vector, block) partial sums
-    uint32_t *counters;  // per vector, zero between launches
+    uint32_t *counters;  // reserved
     double *dst;         // RED_STORE target, indexed by vector
     double *gam;
     double *alpha;

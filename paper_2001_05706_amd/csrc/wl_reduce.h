@@ -1,10 +1,9 @@
 // wl_reduce.h -- deterministic FP64 reductions for wave64 blocks.
 //
 // Per block: 64-lane butterfly shuffles, then one LDS slot per wave, then the
-// first wave; the block's partial goes to a per-(vector, block) slot.  The last
-// block of a vector to arrive (atomic counter) adds that vector's partials in
-// a fixed order and runs the finishing step, so the result does not depend on
-// block scheduling and costs no extra launch.
+// first wave; the block's partial goes to a per-(vector, block) slot, and a
+// finishing kernel adds each vector's partials in a fixed order, so the result
+// does not depend on block scheduling.
 #pragma once
 
 #include "wl_launch.h"
@@ -64,29 +63,15 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, double s)
 }
 
 // Called by every thread of the block (uniform control flow) with its own
-// contribution `mine`.
-__device__ __forceinline__ void block_reduce_finish(const RedSpec &r, int v, int nblk, int pslot0, int lblk,
-                                                    double mine)
+// contribution `mine`: the block's sum goes to its partial slot.  The slots of
+// a vector are added in a fixed order by k_red_finalize after the producing
+// kernel ends; the kernel boundary makes the partials visible without any
+// device-scope fence inside the producer (on gfx950 such a fence writes back
+// the XCD's L2 and costs far more than a separate finishing launch).
+__device__ __forceinline__ void block_reduce_store(const RedSpec &r, int pslot0, int lblk, double mine)
 {
-    __shared__ int is_last;
     const double bs = block_sum(mine);
-    if (threadIdx.x == 0) {
-        r.partials[pslot0 + lblk] = bs;
-        __threadfence();
-        const uint32_t prev = atomicAdd(&r.counters[v], 1u);
-        is_last = (prev == (uint32_t)(nblk - 1));
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
-        s += __hip_atomic_load(&r.partials[pslot0 + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s = block_sum(s);
-    if (threadIdx.x == 0) {
-        red_finalize(r, v, s);
-        __hip_atomic_store(&r.counters[v], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) r.partials[pslot0 + lblk] = bs;
 }
 
 template <class T> __device__ __forceinline__ double site_norm2(const T o[24])

@@ -1,0 +1,103 @@
+"""Full-size GPU cases of the benchmark configurations, checked through the
+FP64 oracle where it can afford it (whole-lattice true residuals, one sampled
+right-hand side of the sign function) and through properties that hold at any
+size otherwise.
+
+  mixed precision   32^3 x 64, eps 0.3 links, kappa 0.1248, FP16 and BF16
+                    sloppy with recon-12 links, true residual 1e-10
+  batched           24^3 x 48, the 12 spin-colour point sources at the origin
+  uneven batch      4 x {8^4, 12^4, 16^3 x 32, 24^3 x 48} in one batched solve
+  sign function     16^3 x 32, eps 0.2 links, rho 1.5, degree 200, 12 RHS, FP32
+"""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+import oracle
+from tests.gpu_util import from_dev, need_gpu, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def true_resid(L, U, eta, psi, kappa):
+    r = eta - oracle.wilson(L, U, psi, kappa)
+    return np.linalg.norm(r.reshape(r.shape[0], -1), axis=1) / np.linalg.norm(eta.reshape(eta.shape[0], -1), axis=1)
+
+
+@pytest.mark.parametrize("sloppy", ["f16", "bf16"])
+def test_mixed_precision_32c64(sloppy):
+    w = need_gpu()
+    L = (32, 32, 32, 64)
+    U = li.near_identity_links(L, 0.3, 1003)
+    eta = li.gaussian_spinor(L, 2003)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.wilson_cg(g, to_dev(eta), x, 1, 0.1248, 1e-10, 3000, sloppy, 12, 0.1)
+    psi = from_dev(x, eta.shape)
+    tr = true_resid(L, U, eta, psi, 0.1248)
+    assert info[0]["converged"] and tr[0] <= 1e-10, (info, tr)
+    assert abs(info[0]["true_resid"] - tr[0]) <= 1e-3 * tr[0]
+    g.close()
+
+
+def test_twelve_point_sources_24c48():
+    w = need_gpu()
+    L = (24, 24, 24, 48)
+    U = li.near_identity_links(L, 0.3, 1004)
+    eta = li.point_sources(L)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.wilson_cg(g, to_dev(eta), x, 12, 0.1245, 1e-10, 3000, "f32", 12, 0.1)
+    psi = from_dev(x, eta.shape)
+    tr = true_resid(L, U, eta, psi, 0.1245)
+    assert np.all(tr <= 1e-10) and all(i["converged"] for i in info), tr
+    g.close()
+
+
+def test_uneven_batch_full_size():
+    w = need_gpu()
+    sizes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 48)]
+    specs = [(L, i) for L in sizes for i in range(4)]
+    gs, etas, xs, Us = [], [], [], []
+    for n, (L, i) in enumerate(specs):
+        U = li.near_identity_links(L, 0.3, 3000 + n)
+        Us.append(U)
+        gs.append(w.Gauge(L, to_dev(U)))
+        e = li.gaussian_spinor(L, 4000 + n)
+        etas.append(e)
+        xs.append(to_dev(np.zeros_like(e)))
+    st, info = w.wilson_cg_multi(gs, [to_dev(e) for e in etas], xs, [1] * len(specs), [0.1245] * len(specs),
+                                 1e-10, 3000, "f32", 12, 0.1)
+    for n, (L, i) in enumerate(specs):
+        psi = from_dev(xs[n], etas[n].shape)
+        tr = true_resid(L, Us[n], etas[n], psi, 0.1245)
+        assert info[n]["converged"] and tr[0] <= 1e-10, (L, i, tr)
+    for g in gs:
+        g.close()
+
+
+def test_sign_function_16c32_twelve_rhs():
+    """GPU FP32 on 12 RHS; the oracle recomputes one sampled RHS in full.
+
+    scale = 42.25 bounds lambda_max(H_W^2) for any SU(3) field:
+    |H_W| <= |4 - rho| + |H|/2 <= 2.5 + 4 (|H| <= 8 for unitary links)."""
+    w = need_gpu()
+    L = (16, 16, 16, 32)
+    U = li.near_identity_links(L, 0.2, 1005)
+    psi = li.gaussian_spinor(L, 2005, nrhs=12)
+    rho, deg, lo, hi, scale = 1.5, 200, 0.003, 1.0, 42.25
+    g = w.Gauge(L, to_dev(U))
+    out = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, to_dev(psi), out, 12, rho, deg, lo, hi, scale, "f32", 12)
+    got = from_dev(out, psi.shape)
+    k = 7  # sampled right-hand side
+    ref = oracle.sign_cheb(L, U, psi[k], rho, deg, lo, hi, scale)
+    assert rel(got[k], ref) <= 1e-5
+    # eps^2 = 1 and norm preservation on every RHS (FP32 arithmetic)
+    out2 = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, out, out2, 12, rho, deg, lo, hi, scale, "f32", 12)
+    back = from_dev(out2, psi.shape)
+    for r in range(12):
+        assert rel(back[r], psi[r]) <= 1e-4
+        assert abs(np.linalg.norm(got[r]) / np.linalg.norm(psi[r]) - 1) <= 1e-4
+    g.close()
