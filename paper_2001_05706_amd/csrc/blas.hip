@@ -148,6 +148,117 @@ __global__ __launch_bounds__(256) void k_scale_rsqrt(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
 }
 
+// complex scalar of vector v from two slots
+__device__ __forceinline__ void cscal(const BlasArgs &a, int re_slot, int v, double &re, double &im)
+{
+    re = a.sc[(size_t)re_slot * a.nvec + v];
+    im = a.sc[(size_t)(re_slot + 1) * a.nvec + v];
+}
+
+// y = z * x for complex z and a site of 12 complex numbers
+template <class T> __device__ __forceinline__ void cmul_site(T zr, T zi, const T x[24], T y[24])
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        y[2 * k] = zr * x[2 * k] - zi * x[2 * k + 1];
+        y[2 * k + 1] = zr * x[2 * k + 1] + zi * x[2 * k];
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    double rr, ri, pr, pi, ar, ai, orr, oi;
+    cscal(a, SC_RHO_RE, bm.v, rr, ri);
+    cscal(a, SC_RHOP_RE, bm.v, pr, pi);
+    cscal(a, SC_AL_RE, bm.v, ar, ai);
+    cscal(a, SC_OM_RE, bm.v, orr, oi);
+    // beta = (rho / rho_prev) (alpha / omega)
+    const double d1 = pr * pr + pi * pi, d2 = orr * orr + oi * oi;
+    const double q1r = (rr * pr + ri * pi) / d1, q1i = (ri * pr - rr * pi) / d1;
+    const double q2r = (ar * orr + ai * oi) / d2, q2i = (ai * orr - ar * oi) / d2;
+    const T br = (T)(q1r * q2r - q1i * q2i), bi = (T)(q1r * q2i + q1i * q2r);
+    T p[24], r[24], v[24], t[24];
+    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
+    load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
+    cmul_site((T)orr, (T)oi, v, t);  // omega v
+#pragma unroll
+    for (int k = 0; k < 24; ++k) t[k] = p[k] - t[k];
+    cmul_site(br, bi, t, p);  // beta (p - omega v)
+#pragma unroll
+    for (int k = 0; k < 24; ++k) p[k] += r[k];
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    double ar, ai;
+    cscal(a, SC_AL_RE, bm.v, ar, ai);
+    T r[24], v[24], av[24];
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
+    load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
+    cmul_site((T)ar, (T)ai, v, av);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) r[k] -= av[k];
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_bicg_xr(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    double rv[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        double ar, ai, orr, oi;
+        cscal(a, SC_AL_RE, bm.v, ar, ai);
+        cscal(a, SC_OM_RE, bm.v, orr, oi);
+        T x[24], y[24], z[24], w[24];
+        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, y);  // p
+        cmul_site((T)ar, (T)ai, y, z);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) x[k] += z[k];
+        load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, y);  // s
+        cmul_site((T)orr, (T)oi, y, z);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) x[k] += z[k];
+        store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P>(vbase<P>(a.f[4], vd), nbase(a.fn[4], vd), sd.stride, cb, w);  // t
+        cmul_site((T)orr, (T)oi, w, z);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) y[k] -= z[k];  // r = s - omega t
+        store_spinor<P>(vbase<P>(a.f[3], vd), nbase(a.fn[3], vd), sd.stride, cb, y);
+        load_spinor<P>(vbase<P>(a.f[5], vd), nbase(a.fn[5], vd), sd.stride, cb, w);  // rhat
+        site_cdot(w, y, rv[0], rv[1]);
+        rv[2] = site_norm2(y);
+    }
+    block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_cdot(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    double rv[3] = {0.0, 0.0, 0.0};
+    if (live) {
+        T x[24], y[24];
+        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, y);
+        site_cdot(x, y, rv[0], rv[1]);
+    }
+    block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+}
+
 template <int PD, int PS>
 __global__ __launch_bounds__(256) void k_convert(BlasArgs a)
 {
@@ -176,6 +287,10 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
     case BL_COPY: hipLaunchKernelGGL((k_convert<P, P>), g, b, 0, s, a); break;
     case BL_FILL: hipLaunchKernelGGL(k_fill<P>, g, b, 0, s, a); break;
     case BL_SCALE_RSQRT: hipLaunchKernelGGL(k_scale_rsqrt<P>, g, b, 0, s, a); break;
+    case BL_BICG_P: hipLaunchKernelGGL(k_bicg_p<P>, g, b, 0, s, a); break;
+    case BL_BICG_S: hipLaunchKernelGGL(k_bicg_s<P>, g, b, 0, s, a); break;
+    case BL_BICG_XR: hipLaunchKernelGGL(k_bicg_xr<P>, g, b, 0, s, a); break;
+    case BL_CDOT: hipLaunchKernelGGL(k_cdot<P>, g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -188,10 +303,13 @@ __global__ __launch_bounds__(256) void k_red_finalize(RedSpec r, const VecDesc *
     const int v = blockIdx.x;
     if (active && !active[v]) return;
     const VecDesc vd = vec[v];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < vd.nblk; i += blockDim.x) s += r.partials[vd.pslot0 + i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) red_finalize(r, v, s);
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < r.nv; ++k) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < vd.nblk; i += blockDim.x) s += r.partials[(size_t)(vd.pslot0 + i) * r.nv + k];
+        tot[k] = block_sum(s);
+    }
+    if (threadIdx.x == 0) red_finalize(r, v, tot);
 }
 
 hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s)

@@ -115,7 +115,7 @@ struct Cg {
     {
         WL_TRY(hop(S, P_F64, 18, false, 1, t64, xh, epi(c_plain), no_red(), s, use_active));
         WL_TRY(hop(S, P_F64, 18, false, 0, rh, t64, epi(c_res, 2, xh, bp),
-                   red_spec(S, RED_STORE, S.scal(ExecSet::SC_RR)), s, use_active));
+                   red_spec(S, RED_STORE, S.scal(SC_RR)), s, use_active));
         return WL_OK;
     }
 
@@ -124,10 +124,10 @@ struct Cg {
     {
         WL_TRY(apply_M(sloppy, recon, false, q, p, tl, red_spec(S, RED_ALPHA, nullptr)));
         Field f[4] = {xl, p, rl, q};
-        WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(ExecSet::SC_ALPHA), red_spec(S, RED_STORE, hist_row), s));
+        WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(SC_ALPHA), red_spec(S, RED_STORE, hist_row), s));
         WL_TRY(apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_BETA, nullptr)));
         Field g[2] = {p, sv};
-        WL_TRY(blas(S, BL_XPAY, sloppy, g, 2, S.scal(ExecSet::SC_BETA), no_red(), s));
+        WL_TRY(blas(S, BL_XPAY, sloppy, g, 2, S.scal(SC_BETA), no_red(), s));
         return WL_OK;
     }
 
@@ -217,8 +217,8 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
     // sources, |eta|^2, b', initial guess, first FP64 residual
     WL_TRY(pack(S, eta, 0, cg.eta_e, s));
     WL_TRY(pack(S, eta, 1, cg.eta_o, s));
-    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_e, 1, nullptr, red_spec(S, RED_STORE, S.scal(ExecSet::SC_ETA)), s));
-    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_o, 1, nullptr, red_spec(S, RED_ACCUM, S.scal(ExecSet::SC_ETA)), s));
+    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_e, 1, nullptr, red_spec(S, RED_STORE, S.scal(SC_ETA)), s));
+    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_o, 1, nullptr, red_spec(S, RED_ACCUM, S.scal(SC_ETA)), s));
     WL_TRY(hop(S, P_F64, 18, false, 0, cg.bp, cg.eta_o, cg.epi(cg.c_bp, 1, cg.eta_e), no_red(), s));
     WL_TRY(pack(S, (const double *const *)x, 0, cg.xh, s));
     WL_TRY(cg.residual64());
@@ -228,8 +228,8 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
     std::vector<int> iters(nv, 0), updates(nv, 0), conv(nv, 0), done(nv, 0), stall(nv, 0);
     std::vector<int> zero_src(nv, 0);
     for (int v = 0; v < nv; ++v) {
-        eta_n[v] = std::sqrt(hp[ExecSet::SC_ETA * nv + v]);
-        const double r = std::sqrt(hp[ExecSet::SC_RR * nv + v]);
+        eta_n[v] = std::sqrt(hp[SC_ETA * nv + v]);
+        const double r = std::sqrt(hp[SC_RR * nv + v]);
         target[v] = tol * eta_n[v];
         if (!std::isfinite(eta_n[v]) || !std::isfinite(r))
             return set_error(WL_ERR_NONFINITE, "non-finite source or initial guess (rhs %d)", v);
@@ -301,8 +301,8 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 for (int j = 0; j < ExecSet::SC_N; ++j)
                     WL_HIP(hipMemcpy(&sc[j], S.scal(j), sizeof(double), hipMemcpyDeviceToHost));
                 fprintf(stderr, "[wl cg] chunk k=%d prec=%d rhs0: |r| %.3e -> %.3e  alpha %.3e beta %.3e gamma %.3e bad %d\n",
-                        k, cg.sloppy, std::sqrt(hp[0]), std::sqrt(hp[(size_t)(k - 1) * nv]), sc[ExecSet::SC_ALPHA],
-                        sc[ExecSet::SC_BETA], sc[ExecSet::SC_GAM], (int)hbad[0]);
+                        k, cg.sloppy, std::sqrt(hp[0]), std::sqrt(hp[(size_t)(k - 1) * nv]), sc[SC_ALPHA],
+                        sc[SC_BETA], sc[SC_GAM], (int)hbad[0]);
             }
             std::vector<int> upd(nv, 0), restart(nv, 0);
             bool anyupd = false, anybad = false;
@@ -354,7 +354,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v];
                 WL_TRY(S.upload_active(s));
                 WL_TRY(cg.residual64());
-                WL_HIP(hipMemcpyAsync(hp, S.scal(ExecSet::SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+                WL_HIP(hipMemcpyAsync(hp, S.scal(SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
                 WL_HIP(hipStreamSynchronize(s));
                 bool stalled = false;
                 for (int v = 0; v < nv; ++v) {
@@ -427,12 +427,12 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
     WL_TRY(S.upload_active(s));
     WL_TRY(hop(S, P_F64, 18, false, 1, cg.xo, cg.xh, cg.epi(cg.c_bp, 1, cg.eta_o), no_red(), s));
     WL_TRY(hop(S, P_F64, 18, false, 0, cg.rh, cg.xo, cg.epi(cg.c_tres, 2, cg.xh, cg.eta_e),
-               red_spec(S, RED_STORE, S.scal(ExecSet::SC_RR)), s));
+               red_spec(S, RED_STORE, S.scal(SC_RR)), s));
     WL_TRY(hop(S, P_F64, 18, false, 1, cg.t64, cg.xh, cg.epi(cg.c_tres, 2, cg.xo, cg.eta_o),
-               red_spec(S, RED_ACCUM, S.scal(ExecSet::SC_RR)), s));
+               red_spec(S, RED_ACCUM, S.scal(SC_RR)), s));
     WL_TRY(unpack(S, x, 0, cg.xh, s));
     WL_TRY(unpack(S, x, 1, cg.xo, s));
-    WL_HIP(hipMemcpyAsync(hp, S.scal(ExecSet::SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    WL_HIP(hipMemcpyAsync(hp, S.scal(SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
     WL_HIP(hipStreamSynchronize(s));
     const double t1 = now_s();
     bool allconv = true;

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     const int cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
     const size_t voff = (size_t)vd.site_off * NC;
 
-    double nrm = 0.0;
+    double rv[3] = {0.0, 0.0, 0.0};
     if (cb < sd.Vh) {
         HopSite hs;
         hs.in = (const CH *)a.in + voff;
@@ -77,9 +77,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
             for (int k = 0; k < 24; ++k) o[k] += aj * x[k];
         }
         store_spinor<SP>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
-        if (a.red.kind != RED_NONE) nrm = site_norm2(o);
+        if (a.red.kind != RED_NONE) {
+            if (a.red.mode == RM_NORM) {
+                rv[0] = site_norm2(o);
+            } else {
+                // the X field was read above; this re-read hits in cache
+                const int j = a.red.mode == RM_DOT_X1 ? 1 : 0;
+                T x[24];
+                load_spinor<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+                                sd.stride, cb, x);
+                if (a.red.mode == RM_DOT_X1) {
+                    site_cdot(x, o, rv[0], rv[1]);
+                } else {
+                    site_cdot(o, x, rv[0], rv[1]);
+                    rv[2] = site_norm2(o);
+                }
+            }
+        }
     }
-    if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
+    if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
 }
 
 template <int SP, int GP, int R, int VAR>

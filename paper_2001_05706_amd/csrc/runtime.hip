@@ -266,7 +266,7 @@ wl_status ExecSet::init()
     if (total_sites > (size_t)INT32_MAX / 16) return set_error(WL_ERR_GEOM, "set too large");
     h_active.assign(nvec, 1);
     WL_ALLOC(d_active, sizeof(int32_t) * nvec);
-    WL_ALLOC(partials, sizeof(double) * max_pslots);
+    WL_ALLOC(partials, sizeof(double) * 3 * max_pslots);
     WL_ALLOC(counters, sizeof(uint32_t) * nvec);
     WL_ALLOC(sc, sizeof(double) * SC_N * nvec);
     WL_ALLOC(bad, sizeof(int32_t) * nvec);
@@ -436,19 +436,20 @@ RedSpec no_red()
 {
     RedSpec r{};
     r.kind = RED_NONE;
+    r.nv = 1;
     return r;
 }
 
-RedSpec red_spec(ExecSet &S, int kind, double *dst)
+RedSpec red_spec(ExecSet &S, int kind, double *dst, int nv, int mode)
 {
     RedSpec r{};
     r.kind = kind;
+    r.nv = nv;
+    r.mode = mode;
+    r.nvec = S.nvec;
     r.partials = S.partials;
-    r.counters = S.counters;
+    r.sc = S.sc;
     r.dst = dst;
-    r.gam = S.scal(ExecSet::SC_GAM);
-    r.alpha = S.scal(ExecSet::SC_ALPHA);
-    r.beta = S.scal(ExecSet::SC_BETA);
     r.bad = S.bad;
     return r;
 }
@@ -574,8 +575,10 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
         a.fn[j] = f[j].n;
     }
     a.s0 = s0;
+    a.sc = S.sc;
+    a.nvec = S.nvec;
     a.red = red;
-    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2};
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 8, 2};
     if (op == BL_ACCUM)
         g_bytes_acc += blas_bytes(S, P_F64, 2, use_active) + blas_bytes(S, prec, 2, use_active);
     else

@@ -61,7 +61,7 @@ static wl_status power_lmax(ExecSet &S, double rho, int recon, int iters, const 
     for (size_t i = 0; i < S.systems.size(); ++i) c.insert(c.end(), {4.0 - rho, 0, 0, 0, -0.5});
     const double *coef = nullptr;
     WL_TRY(coef_table(S, c, &coef));
-    double *nw = S.scal(ExecSet::SC_QQ), *nu = S.scal(ExecSet::SC_RR);
+    double *nw = S.scal(SC_QQ), *nu = S.scal(SC_RR);
     // normalise the start vector
     WL_TRY(blas(S, BL_NORM2, P_F64, &u[0], 1, nullptr, red_spec(S, RED_STORE, nu), s));
     WL_TRY(blas(S, BL_NORM2, P_F64, &u[1], 1, nullptr, red_spec(S, RED_ACCUM, nu), s));

@@ -104,7 +104,7 @@ public:
     wl_status upload_active(hipStream_t s);
 
     // reduction state (per vector unless noted)
-    double *partials = nullptr;  // max slots over layouts (B = 64)
+    double *partials = nullptr;  // max slots over layouts (B = 64), 3 values each
     uint32_t *counters = nullptr;
     double *sc = nullptr;        // scalar arena, see SC_* below
     int32_t *bad = nullptr;
@@ -112,7 +112,7 @@ public:
     double *h_pinned = nullptr;  // pinned host mirror of hist, scalars and flags
     static constexpr int kHist = 64;
 
-    enum { SC_ALPHA = 0, SC_BETA, SC_GAM, SC_QQ, SC_RR, SC_ETA, SC_TMP, SC_N };
+    static constexpr int SC_N = SC_COUNT;  // scalar slots per vector (ScSlot)
     double *scal(int which) { return sc + (size_t)which * nvec; }
 
     // fields by name, allocated on first use
@@ -140,7 +140,7 @@ struct Epi {
 };
 
 RedSpec no_red();
-RedSpec red_spec(ExecSet &S, int kind, double *dst);
+RedSpec red_spec(ExecSet &S, int kind, double *dst, int nv = 1, int mode = RM_NORM);
 
 // out_p = epilogue(hop(in_{1-p})) on every active vector of the set
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int out_parity, const Field &out, const Field &in,

@@ -12,9 +12,12 @@ struct BlasArgs {
     const int32_t *active;
     int32_t nblocks;
     int32_t pad_;
-    void *f[4];
-    float *fn[4];
+    void *f[6];
+    float *fn[6];
     const double *s0;  // per-vector scalar (alpha or beta)
+    const double *sc;  // scalar slots of the set (ScSlot), for complex scalars
+    int32_t nvec;
+    int32_t pad2_;
     RedSpec red;
 };
 
@@ -46,6 +49,11 @@ enum BlasOp {
     BL_COPY = 5,       // y = x                                      f = {y, x}
     BL_FILL = 6,       // x = deterministic pattern (benchmark operands)  f = {x}
     BL_SCALE_RSQRT = 7,// x *= 1/sqrt(s0[v])                         f = {x}
+    // BiCGStab (complex scalars from the slots):
+    BL_BICG_P = 8,     // p = r + beta (p - omega v), beta = (rho/rho_prev)(alpha/omega)   f = {p, r, v}
+    BL_BICG_S = 9,     // s = r - alpha v                                                   f = {s, r, v}
+    BL_BICG_XR = 10,   // x += alpha p + omega s; r = s - omega t; <rhat, r>, |r|^2         f = {x, p, s, r, t, rhat}
+    BL_CDOT = 11,      // <a, b>                                                            f = {a, b}
 };
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
 // fixed-order sum of each active vector's block partials and the reduction's finishing step

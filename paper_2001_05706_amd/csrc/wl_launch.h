@@ -38,26 +38,47 @@ WL_HD int xcd_remap(int h, int nb)
     return k * q + (k < r ? k : r) + i;
 }
 
-// Reduction of a per-site scalar to one FP64 number per vector (block partials,
-// then a fixed-order finishing pass), and the finishing step applied to it.
+// Per-vector scalar slots of a set: scalar `slot` of vector v lives at
+// sc[slot * nvec + v].  Complex scalars use two slots (re, im).
+enum ScSlot {
+    SC_ALPHA = 0, SC_BETA, SC_GAM, SC_QQ, SC_RR, SC_ETA, SC_TMP,
+    SC_RHO_RE, SC_RHO_IM,      // BiCGStab rho = <rhat, r>
+    SC_RHOP_RE, SC_RHOP_IM,    // rho of the previous iteration
+    SC_AL_RE, SC_AL_IM,        // complex alpha
+    SC_OM_RE, SC_OM_IM,        // complex omega
+    SC_COUNT
+};
+
+// Reduction of per-site values (1 to 3 FP64 numbers per vector: block
+// partials, then a fixed-order finishing pass), and the finishing step.
 enum RedKind {
     RED_NONE = 0,
-    RED_STORE = 1,   // dst[v] = sum
-    RED_ALPHA = 2,   // alpha[v] = gam[v] / sum        (sum = |q|^2)
-    RED_BETA = 3,    // beta[v] = sum / gam[v]; gam[v] = sum
-    RED_GAMMA = 4,   // gam[v] = sum
-    RED_ACCUM = 5,   // dst[v] += sum
+    RED_STORE = 1,        // dst[v] = s0
+    RED_ALPHA = 2,        // alpha = gam / s0           (s0 = |q|^2)
+    RED_BETA = 3,         // beta = s0 / gam; gam = s0
+    RED_GAMMA = 4,        // gam = s0
+    RED_ACCUM = 5,        // dst[v] += s0
+    RED_CDOT_RHO = 6,     // rho = s0 + i s1
+    RED_BICG_ALPHA = 7,   // alpha = rho / (s0 + i s1); rho_prev = rho
+    RED_BICG_OMEGA = 8,   // omega = (s0 + i s1) / s2
+    RED_BICG_RHO = 9,     // rho = s0 + i s1; dst[v] = s2
+};
+
+// What the hop epilogue reduces (RedSpec::mode)
+enum RedMode {
+    RM_NORM = 0,    // |out|^2                             (1 value)
+    RM_DOT_X1 = 1,  // <X1, out>                            (2 values)
+    RM_OUT_X0 = 2,  // <out, X0>, |out|^2                   (3 values)
 };
 
 struct RedSpec {
     int32_t kind;
-    int32_t pad_;
-    double *partials;    // per (vector, block) partial sums
-    uint32_t *counters;  // reserved
-    double *dst;         // RED_STORE target, indexed by vector
-    double *gam;
-    double *alpha;
-    double *beta;
+    int32_t nv;          // values per site (1..3)
+    int32_t mode;        // RedMode for hop epilogues
+    int32_t nvec;        // vectors of the set (scalar-slot stride)
+    double *partials;    // per (vector, block) partial sums, nv values each
+    double *sc;          // scalar slots (ScSlot)
+    double *dst;         // RED_STORE / RED_ACCUM / RED_BICG_RHO target, indexed by vector
     int32_t *bad;        // per-vector non-finite flag (bit 0)
 };
 

@@ -35,31 +35,53 @@ __device__ __forceinline__ double block_sum(double v)
     return r;
 }
 
-__device__ __forceinline__ void red_finalize(const RedSpec &r, int v, double s)
+__device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const double *s)
 {
-    if (!isfinite(s) && r.bad) r.bad[v] |= 1;
+    bool finite = true;
+    for (int k = 0; k < r.nv; ++k) finite = finite && isfinite(s[k]);
+    double *sc = r.sc;
+    const int n = r.nvec;
+#define WL_SC(slot) sc[(slot) * n + v]
     switch (r.kind) {
-    case RED_STORE:
-        r.dst[v] = s;
-        break;
-    case RED_ALPHA:
-        r.alpha[v] = s > 0.0 ? r.gam[v] / s : 0.0;
-        break;
+    case RED_STORE: r.dst[v] = s[0]; break;
+    case RED_ALPHA: WL_SC(SC_ALPHA) = s[0] > 0.0 ? WL_SC(SC_GAM) / s[0] : 0.0; break;
     case RED_BETA: {
-        const double g = r.gam[v];
-        r.beta[v] = g > 0.0 ? s / g : 0.0;
-        r.gam[v] = s;
+        const double g = WL_SC(SC_GAM);
+        WL_SC(SC_BETA) = g > 0.0 ? s[0] / g : 0.0;
+        WL_SC(SC_GAM) = s[0];
         break;
     }
-    case RED_GAMMA:
-        r.gam[v] = s;
+    case RED_GAMMA: WL_SC(SC_GAM) = s[0]; break;
+    case RED_ACCUM: r.dst[v] += s[0]; break;
+    case RED_CDOT_RHO:
+        WL_SC(SC_RHO_RE) = s[0];
+        WL_SC(SC_RHO_IM) = s[1];
         break;
-    case RED_ACCUM:
-        r.dst[v] += s;
-        break;
-    default:
+    case RED_BICG_ALPHA: {
+        // alpha = rho / d, a zero d is a breakdown: reported as non-finite
+        const double dr = s[0], di = s[1], d2 = dr * dr + di * di;
+        const double rr = WL_SC(SC_RHO_RE), ri = WL_SC(SC_RHO_IM);
+        if (!(d2 > 0.0)) finite = false;
+        WL_SC(SC_AL_RE) = d2 > 0.0 ? (rr * dr + ri * di) / d2 : 0.0;
+        WL_SC(SC_AL_IM) = d2 > 0.0 ? (ri * dr - rr * di) / d2 : 0.0;
+        WL_SC(SC_RHOP_RE) = rr;
+        WL_SC(SC_RHOP_IM) = ri;
         break;
     }
+    case RED_BICG_OMEGA:
+        if (!(s[2] > 0.0)) finite = false;
+        WL_SC(SC_OM_RE) = s[2] > 0.0 ? s[0] / s[2] : 0.0;
+        WL_SC(SC_OM_IM) = s[2] > 0.0 ? s[1] / s[2] : 0.0;
+        break;
+    case RED_BICG_RHO:
+        WL_SC(SC_RHO_RE) = s[0];
+        WL_SC(SC_RHO_IM) = s[1];
+        r.dst[v] = s[2];
+        break;
+    default: break;
+    }
+#undef WL_SC
+    if (!finite && r.bad) r.bad[v] |= 1;
 }
 
 // Called by every thread of the block (uniform control flow) with its own
@@ -71,7 +93,29 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, double s)
 __device__ __forceinline__ void block_reduce_store(const RedSpec &r, int pslot0, int lblk, double mine)
 {
     const double bs = block_sum(mine);
-    if (threadIdx.x == 0) r.partials[pslot0 + lblk] = bs;
+    if (threadIdx.x == 0) r.partials[(size_t)(pslot0 + lblk) * r.nv] = bs;
+}
+
+// nv values per thread (nv = r.nv <= 3)
+__device__ __forceinline__ void block_reduce_store_n(const RedSpec &r, int pslot0, int lblk, const double *mine)
+{
+    for (int k = 0; k < r.nv; ++k) {
+        const double bs = block_sum(mine[k]);
+        if (threadIdx.x == 0) r.partials[(size_t)(pslot0 + lblk) * r.nv + k] = bs;
+    }
+}
+
+// <a, b> = sum conj(a) b over one site (12 complex numbers)
+template <class T> __device__ __forceinline__ void site_cdot(const T a[24], const T b[24], double &re, double &im)
+{
+    T sr = 0, si = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        sr += a[2 * k] * b[2 * k] + a[2 * k + 1] * b[2 * k + 1];
+        si += a[2 * k] * b[2 * k + 1] - a[2 * k + 1] * b[2 * k];
+    }
+    re = (double)sr;
+    im = (double)si;
 }
 
 template <class T> __device__ __forceinline__ double site_norm2(const T o[24])
