@@ -321,6 +321,20 @@ def main():
                        "true_resid": inf["true_resid"]}
             log("solve %s: %.2f ms, %d iters, resid %.2e" % (sl, min(ts) * 1e3, inf["iters"], inf["true_resid"]))
         out["cg_time_to_1e-10_ms"] = cmp
+        # BiCGStab on the Schur system, same workload and stopping rule
+        bic = {}
+        for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12)]:
+            def run_b():
+                x.zero_()
+                return w.wilson_bicgstab(g, etad, x, 1, kappa, tol, maxiter, sl, rc, a.delta, stream=stream)[1][0]
+            try:
+                tb_, ib_ = _timed(torch, run_b)
+                bic[sl] = {"ms": round(tb_ * 1e3, 3), "iters": ib_["iters"], "updates": ib_["reliable_updates"],
+                           "true_resid": ib_["true_resid"]}
+            except w.WilsonError as e:
+                bic[sl] = {"error": str(e)}
+            log("bicgstab %s: %s" % (sl, bic[sl]))
+        out["bicgstab_time_to_1e-10_ms"] = bic
         if "ms" in cmp.get("f64", {}) and "ms" in cmp.get(a.sloppy, {}):
             out["cg_speedup_vs_fp64"] = round(cmp["f64"]["ms"] / cmp[a.sloppy]["ms"], 3)
     if "dslash" in extras:

@@ -127,6 +127,18 @@ wl_status wilson_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, doub
                     int32_t maxiter, wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info,
                     void *stream);
 
+/* Solve D psi = eta as wilson_cg does, but with BiCGStab on the even-odd
+ * Schur system M x = b' itself instead of CG on its normal equations: two
+ * applications of M per iteration, complex BiCGStab scalars and dot products
+ * in FP64, the same mixed-precision reliable updates (r replaced by the FP64
+ * residual, rho recomputed) and the same stopping rule on the FP64 residual.
+ * A breakdown (<rhat, M p> = 0 or |M s| = 0) or a non-finite sloppy value
+ * restarts from the FP64 solution with a new shadow residual.  Arguments,
+ * ownership and errors as in wilson_cg.  Synchronises `stream`. */
+wl_status wilson_bicgstab(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double tol,
+                          int32_t maxiter, wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info,
+                          void *stream);
+
 /* Solve nsys independent systems (each its own gauge handle and geometry,
  * nrhs[i] right-hand sides, kappa[i]) together: every kernel launch of an
  * iteration covers all still-unconverged right-hand sides of all systems,

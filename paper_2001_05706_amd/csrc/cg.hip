@@ -1,7 +1,8 @@
-// cg.hip -- even-odd preconditioned CG on the normal equations (CGNR) for the
-// Wilson operator, mixed precision with FP64 reliable updates, for one set of
-// systems x right-hand sides at once (QUDA_DIRAC_WILSON of Table 1; the
-// mixed-precision inverters of the QUDA line of work cited in Section 1).
+// cg.hip -- even-odd preconditioned Krylov solvers for the Wilson operator,
+// mixed precision with FP64 reliable updates, for one set of systems x
+// right-hand sides at once (QUDA_DIRAC_WILSON of Table 1; the mixed-precision
+// inverters of the QUDA line of work cited in Section 1): CG on the normal
+// equations (CGNR) and BiCGStab on the Schur system itself.
 //
 //   b' = eta_e + kappa D_eo eta_o,   M = 1 - kappa^2 D_eo D_oe,
 //   M^+ = 1 - kappa^2 D_oe^+ D_eo^+ (dagger hops in the same order).
@@ -17,6 +18,16 @@
 // that fail to halve the FP64 residual raise the sloppy precision one step.
 // Finally psi_o = eta_o + kappa D_oe psi_e and the true residual
 // |eta - D psi| / |eta| is computed in FP64 with the whole-lattice operator.
+//
+// BiCGStab (van der Vorst) on M x = b' with shadow residual rhat = r_0:
+//   beta = (rho / rho_prev)(alpha / omega); p = r + beta (p - omega v);
+//   v = M p, alpha = rho / <rhat, v>; s = r - alpha v; t = M s,
+//   omega = <t, s> / |t|^2; x += alpha p + omega s; r = s - omega t;
+//   rho_prev = rho, rho = <rhat, r>.
+// <rhat, v> and (<t, s>, |t|^2) are reduced in the epilogue of the second hop of
+// M; <rhat, r> and |r|^2 in the x/r update.  A reliable update replaces r and
+// recomputes rho; a breakdown (zero <rhat, v> or |t|) or a non-finite value
+// restarts from the FP64 accumulator with rhat = r.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -37,9 +48,12 @@ static hipStream_t capture_stream()
     return cs;
 }
 
+enum { M_CGNR = 0, M_BICGSTAB = 1 };
+
 struct Cg {
     ExecSet &S;
     hipStream_t s;
+    int method = M_CGNR;
     int recon;
     double tol;
     int maxiter;
@@ -48,7 +62,8 @@ struct Cg {
     bool use_graphs;
 
     Field eta_e, eta_o, bp, xh, rh, t64, xo;  // FP64
-    Field xl, rl, p, q, sv, tl;               // sloppy
+    Field xl, rl, p, q, sv, tl;               // sloppy; BiCGStab: q = v, sv = s
+    Field tb, rhat;                           // sloppy, BiCGStab only: t, shadow residual
     const double *c_plain = nullptr, *c_bp = nullptr, *c_M = nullptr, *c_res = nullptr, *c_tres = nullptr;
 
     Cg(ExecSet &S_, hipStream_t s_) : S(S_), s(s_) {}
@@ -61,6 +76,10 @@ struct Cg {
         WL_TRY(S.field("cg_q", sloppy, &q));
         WL_TRY(S.field("cg_s", sloppy, &sv));
         WL_TRY(S.field("cg_t", sloppy, &tl));
+        if (method == M_BICGSTAB) {
+            WL_TRY(S.field("bi_t", sloppy, &tb));
+            WL_TRY(S.field("bi_rhat", sloppy, &rhat));
+        }
         return WL_OK;
     }
 
@@ -119,9 +138,26 @@ struct Cg {
         return WL_OK;
     }
 
-    // one CGNR iteration in the sloppy precision; hist_row receives |r|^2
+    // one iteration in the sloppy precision; hist_row receives |r|^2
     wl_status iteration(double *hist_row)
     {
+        if (method == M_BICGSTAB) {
+            // p = r + beta (p - omega v);  v = M p, alpha = rho / <rhat, v>;  s = r - alpha v;
+            // t = M s, omega = <t, s> / |t|^2;  x += alpha p + omega s;  r = s - omega t, rho = <rhat, r>
+            Field fp[3] = {p, rl, q};
+            WL_TRY(blas(S, BL_BICG_P, sloppy, fp, 3, nullptr, no_red(), s));
+            WL_TRY(hop(S, sloppy, recon, false, 1, tl, p, epi(c_plain), no_red(), s));
+            WL_TRY(hop(S, sloppy, recon, false, 0, q, tl, epi(c_M, 2, p, rhat),
+                       red_spec(S, RED_BICG_ALPHA, nullptr, 2, RM_DOT_X1), s));
+            Field fs[3] = {sv, rl, q};
+            WL_TRY(blas(S, BL_BICG_S, sloppy, fs, 3, nullptr, no_red(), s));
+            WL_TRY(hop(S, sloppy, recon, false, 1, tl, sv, epi(c_plain), no_red(), s));
+            WL_TRY(hop(S, sloppy, recon, false, 0, tb, tl, epi(c_M, 1, sv),
+                       red_spec(S, RED_BICG_OMEGA, nullptr, 3, RM_OUT_X0), s));
+            Field fx[6] = {xl, p, sv, rl, tb, rhat};
+            WL_TRY(blas(S, BL_BICG_XR, sloppy, fx, 6, nullptr, red_spec(S, RED_BICG_RHO, hist_row, 3), s));
+            return WL_OK;
+        }
         WL_TRY(apply_M(sloppy, recon, false, q, p, tl, red_spec(S, RED_ALPHA, nullptr)));
         Field f[4] = {xl, p, rl, q};
         WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(SC_ALPHA), red_spec(S, RED_STORE, hist_row), s));
@@ -133,8 +169,55 @@ struct Cg {
 
     double iteration_bytes()
     {
+        if (method == M_BICGSTAB)  // 4 hops (+3 epilogue reads), p (4), s (3), x/r (7)
+            return 4 * hop_bytes(S, sloppy, recon, true) + blas_bytes(S, sloppy, 3 + 4 + 3 + 7, true);
         return 4 * hop_bytes(S, sloppy, recon, true) + 2 * blas_bytes(S, sloppy, 1, true) +
                blas_bytes(S, sloppy, 6, true) + blas_bytes(S, sloppy, 3, true);
+    }
+
+    // After the FP64 residual rh is fresh: continue (cont) or restart (restart)
+    // the sloppy recurrence of the active vectors.  Masks are host vectors.
+    wl_status refresh(const std::vector<int> &cont, const std::vector<int> &restart)
+    {
+        const int nv = S.nvec;
+        std::vector<int> both(nv);
+        bool anyc = false, anyr = false;
+        for (int v = 0; v < nv; ++v) {
+            both[v] = cont[v] || restart[v];
+            anyc = anyc || cont[v];
+            anyr = anyr || restart[v];
+        }
+        if (!anyc && !anyr) return WL_OK;
+        S.h_active.assign(both.begin(), both.end());
+        WL_TRY(S.upload_active(s));
+        WL_TRY(convert(S, rl, rh, s));
+        if (method == M_CGNR) {
+            WL_TRY(apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_GAMMA, nullptr)));
+            if (anyr) {  // p = s: a fresh search direction
+                S.h_active.assign(restart.begin(), restart.end());
+                WL_TRY(S.upload_active(s));
+                Field cp[2] = {p, sv};
+                WL_TRY(blas(S, BL_COPY, sloppy, cp, 2, nullptr, no_red(), s));
+            }
+            return WL_OK;
+        }
+        if (anyc) {  // keep rhat, p, v, alpha, omega, rho_prev; rho = <rhat, r>
+            S.h_active.assign(cont.begin(), cont.end());
+            WL_TRY(S.upload_active(s));
+            Field cd[2] = {rhat, rl};
+            WL_TRY(blas(S, BL_CDOT, sloppy, cd, 2, nullptr, red_spec(S, RED_CDOT_RHO, nullptr, 2), s));
+        }
+        if (anyr) {  // new shadow residual rhat = r, p = v = 0, rho = rho_prev = |r|^2, alpha = omega = 1
+            S.h_active.assign(restart.begin(), restart.end());
+            WL_TRY(S.upload_active(s));
+            Field cp[2] = {rhat, rl};
+            WL_TRY(blas(S, BL_COPY, sloppy, cp, 2, nullptr, no_red(), s));
+            WL_TRY(blas(S, BL_ZERO, sloppy, &p, 1, nullptr, no_red(), s));
+            WL_TRY(blas(S, BL_ZERO, sloppy, &q, 1, nullptr, no_red(), s));
+            Field cd[2] = {rhat, rl};
+            WL_TRY(blas(S, BL_CDOT, sloppy, cd, 2, nullptr, red_spec(S, RED_BICG_INIT, nullptr, 2), s));
+        }
+        return WL_OK;
     }
 
     wl_status chunk(int k)
@@ -143,7 +226,8 @@ struct Cg {
             for (int j = 0; j < k; ++j) WL_TRY(iteration(S.hist + (size_t)j * S.nvec));
             return WL_OK;
         }
-        const std::string key = "cg/" + std::to_string(k) + "/" + std::to_string(sloppy) + "/" + std::to_string(recon);
+        const std::string key = "cg/" + std::to_string(method) + "/" + std::to_string(k) + "/" +
+                                std::to_string(sloppy) + "/" + std::to_string(recon);
         auto it = S.graphs.find(key);
         if (it == S.graphs.end()) {
             const SysDesc *tab = nullptr;  // packed links and tables exist before capture
@@ -193,11 +277,12 @@ static int round_chunk(double k)
 
 // Solve the systems of S for the canonical sources eta[i] into x[i] (guesses on entry).
 wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int recon, double tol, int maxiter,
-                 int sloppy, double delta, wl_solve_info *info, hipStream_t s)
+                 int sloppy, double delta, wl_solve_info *info, hipStream_t s, int method = M_CGNR)
 {
     const double t0 = now_s();
     g_bytes_acc = 0.0;
     Cg cg(S, s);
+    cg.method = method;
     cg.recon = recon;
     cg.tol = tol;
     cg.maxiter = maxiter;
@@ -260,10 +345,11 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
 
     if (any) {
         WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
-        WL_TRY(convert(S, cg.rl, cg.rh, s));
-        WL_TRY(cg.apply_M(cg.sloppy, recon, true, cg.sv, cg.rl, cg.tl, red_spec(S, RED_GAMMA, nullptr)));
-        Field cp[2] = {cg.p, cg.sv};
-        WL_TRY(blas(S, BL_COPY, cg.sloppy, cp, 2, nullptr, no_red(), s));
+        {
+            std::vector<int> none(nv, 0), start(nv, 0);
+            for (int v = 0; v < nv; ++v) start[v] = !done[v];
+            WL_TRY(cg.refresh(none, start));
+        }
         int k = 4;
         bool first = true;
         // FP16/BF16 recurrences drift faster: shorter chunks, so updates are not late
@@ -272,14 +358,31 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
         std::vector<double> rmin(nv);
         for (int v = 0; v < nv; ++v) rmin[v] = rmax[v];
         // raise the sloppy precision one step; p is converted (restarted vectors overwrite it)
-        auto escalate = [&](const char *why) -> wl_status {
+        // `folded` marks the vectors whose sloppy solution is already in the FP64
+        // accumulator with a fresh FP64 residual; the others are folded in here first
+        auto escalate = [&](const char *why, const std::vector<int> &folded) -> wl_status {
+            bool rest = false;
+            for (int v = 0; v < nv; ++v) {
+                S.h_active[v] = !done[v] && !folded[v];
+                rest = rest || S.h_active[v];
+            }
+            if (rest) {
+                WL_TRY(S.upload_active(s));
+                Field ac[2] = {cg.xh, cg.xl};
+                WL_TRY(blas(S, BL_ACCUM, cg.sloppy, ac, 2, nullptr, no_red(), s));
+                WL_TRY(cg.residual64());
+            }
             const int next = cg.sloppy == P_F32 ? P_F64 : P_F32;
-            Field p_old = cg.p;
+            Field p_old = cg.p, v_old = cg.q, rhat_old = cg.rhat;
             cg.sloppy = next;
             WL_TRY(cg.sloppy_fields());
             for (int v = 0; v < nv; ++v) S.h_active[v] = !done[v];
             WL_TRY(S.upload_active(s));
             WL_TRY(convert(S, cg.p, p_old, s));
+            if (cg.method == M_BICGSTAB) {
+                WL_TRY(convert(S, cg.q, v_old, s));
+                WL_TRY(convert(S, cg.rhat, rhat_old, s));
+            }
             WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
             ++escalations;
             if (trace) fprintf(stderr, "[wl cg] %s: sloppy precision raised to %d\n", why, cg.sloppy);
@@ -382,7 +485,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 if (status != WL_OK) break;
                 // after the FP64 accumulation above, so no vector loses its sloppy progress
                 if ((stalled || anybad) && cg.sloppy != P_F64) {
-                    WL_TRY(escalate(anybad ? "non-finite sloppy iterate" : "stagnation"));
+                    WL_TRY(escalate(anybad ? "non-finite sloppy iterate" : "stagnation", upd));
                     WL_HIP(hipMemsetAsync(S.bad, 0, sizeof(int32_t) * nv, s));
                     for (int v = 0; v < nv; ++v)
                         if (!done[v]) {
@@ -390,20 +493,12 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                             stall[v] = 0;
                         }
                 }
-                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v] && !done[v];
-                WL_TRY(S.upload_active(s));
-                WL_TRY(convert(S, cg.rl, cg.rh, s));
-                WL_TRY(cg.apply_M(cg.sloppy, recon, true, cg.sv, cg.rl, cg.tl, red_spec(S, RED_GAMMA, nullptr)));
-                bool anyrestart = false;
+                std::vector<int> cont(nv, 0), rst(nv, 0);
                 for (int v = 0; v < nv; ++v) {
-                    S.h_active[v] = restart[v] && !done[v];
-                    anyrestart = anyrestart || S.h_active[v];
+                    cont[v] = upd[v] && !done[v] && !restart[v];
+                    rst[v] = restart[v] && !done[v];
                 }
-                if (anyrestart) {  // p = s: a fresh search direction
-                    WL_TRY(S.upload_active(s));
-                    Field cp[2] = {cg.p, cg.sv};
-                    WL_TRY(blas(S, BL_COPY, cg.sloppy, cp, 2, nullptr, no_red(), s));
-                }
+                WL_TRY(cg.refresh(cont, rst));
             }
             bool left = false;
             for (int v = 0; v < nv; ++v) {
@@ -489,6 +584,24 @@ wl_status wilson_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, doub
     const double *e[1] = {eta};
     double *xx[1] = {x};
     return run_cg(*S, e, xx, recon, tol, maxiter, sloppy, delta, info, (hipStream_t)stream);
+}
+
+wl_status wilson_bicgstab(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double tol,
+                          int32_t maxiter, wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info,
+                          void *stream)
+{
+    clear_error();
+    WL_TRY(check_gauge(U));
+    if (nrhs < 1) return set_error(WL_ERR_ARG, "nrhs = %d must be >= 1", nrhs);
+    if (!(kappa > 0) || !std::isfinite(kappa)) return set_error(WL_ERR_ARG, "kappa must be > 0 and finite");
+    WL_TRY(check_solver_args(tol, maxiter, sloppy, recon, delta));
+    WL_TRY(check_field(eta, U, nrhs, "eta"));
+    WL_TRY(check_field(x, U, nrhs, "x"));
+    ExecSet *S = nullptr;
+    WL_TRY(get_set({SysEntry{U, nrhs, kappa}}, &S));
+    const double *e[1] = {eta};
+    double *xx[1] = {x};
+    return run_cg(*S, e, xx, recon, tol, maxiter, sloppy, delta, info, (hipStream_t)stream, M_BICGSTAB);
 }
 
 wl_status wilson_cg_multi(int32_t nsys, const wl_gauge *U, const double *const *eta, double *const *x,

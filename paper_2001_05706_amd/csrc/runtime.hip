@@ -578,7 +578,7 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.sc = S.sc;
     a.nvec = S.nvec;
     a.red = red;
-    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 8, 2};
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2};
     if (op == BL_ACCUM)
         g_bytes_acc += blas_bytes(S, P_F64, 2, use_active) + blas_bytes(S, prec, 2, use_active);
     else

@@ -62,6 +62,7 @@ enum RedKind {
     RED_BICG_ALPHA = 7,   // alpha = rho / (s0 + i s1); rho_prev = rho
     RED_BICG_OMEGA = 8,   // omega = (s0 + i s1) / s2
     RED_BICG_RHO = 9,     // rho = s0 + i s1; dst[v] = s2
+    RED_BICG_INIT = 10,   // rho = rho_prev = s0 + i s1; alpha = omega = 1
 };
 
 // What the hop epilogue reduces (RedSpec::mode)

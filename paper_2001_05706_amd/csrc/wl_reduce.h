@@ -73,6 +73,13 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const doub
         WL_SC(SC_OM_RE) = s[2] > 0.0 ? s[0] / s[2] : 0.0;
         WL_SC(SC_OM_IM) = s[2] > 0.0 ? s[1] / s[2] : 0.0;
         break;
+    case RED_BICG_INIT:
+        WL_SC(SC_RHO_RE) = WL_SC(SC_RHOP_RE) = s[0];
+        WL_SC(SC_RHO_IM) = WL_SC(SC_RHOP_IM) = s[1];
+        WL_SC(SC_AL_RE) = WL_SC(SC_OM_RE) = 1.0;
+        WL_SC(SC_AL_IM) = WL_SC(SC_OM_IM) = 0.0;
+        if (!(s[0] * s[0] + s[1] * s[1] > 0.0)) finite = false;
+        break;
     case RED_BICG_RHO:
         WL_SC(SC_RHO_RE) = s[0];
         WL_SC(SC_RHO_IM) = s[1];

@@ -58,6 +58,7 @@ SIGNATURES = [
     ("wl_gauge_destroy", None, [_P]),
     ("wilson_dslash", _i32, [_P, _P, _P, _i32, _d, _i32, _i32, _i32, _i32, _P]),
     ("wilson_cg", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _i32, _i32, _d, ctypes.POINTER(WlSolveInfo), _P]),
+    ("wilson_bicgstab", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _i32, _i32, _d, ctypes.POINTER(WlSolveInfo), _P]),
     ("wilson_cg_multi", _i32, [_i32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                ctypes.POINTER(_i32), ctypes.POINTER(_d), _d, _i32, _i32, _i32, _d,
                                ctypes.POINTER(WlSolveInfo), _P]),
@@ -172,6 +173,17 @@ def wilson_cg(U: Gauge, eta, x, nrhs, kappa, tol, maxiter, sloppy="f32", recon=1
     infos = (WlSolveInfo * int(nrhs))()
     st = lib().wilson_cg(U.handle, _ptr(eta, "eta"), _ptr(x, "x"), int(nrhs), float(kappa), float(tol),
                          int(maxiter), _prec(sloppy), int(recon), float(delta), infos, _stream(stream))
+    res = [i.as_dict() for i in infos]
+    if check:
+        _check(st, res)
+    return st, res
+
+
+def wilson_bicgstab(U: Gauge, eta, x, nrhs, kappa, tol, maxiter, sloppy="f32", recon=12, delta=0.1, stream=None,
+                    check=True):
+    infos = (WlSolveInfo * int(nrhs))()
+    st = lib().wilson_bicgstab(U.handle, _ptr(eta, "eta"), _ptr(x, "x"), int(nrhs), float(kappa), float(tol),
+                               int(maxiter), _prec(sloppy), int(recon), float(delta), infos, _stream(stream))
     res = [i.as_dict() for i in infos]
     if check:
         _check(st, res)
