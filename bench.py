@@ -251,12 +251,14 @@ def main():
     # ---- per-kernel timing of the dominant kernel over the same K solves:
     # HIP events bracket every hop launch on its stream (graph replay off)
     w.wl_prof_enable(True)
+    w.wl_prof_select(a.sloppy)  # the dominant kernel: the sloppy-precision hop
     w.wl_prof_read()
     for _ in range(a.steps):
         solve(a.sloppy, a.recon)
     torch.cuda.synchronize()
     n_hop, hop_ms, hop_gb = w.wl_prof_read()
     w.wl_prof_enable(False)
+    w.wl_prof_select(-1)
     hop_avg_us = hop_ms * 1e3 / max(n_hop, 1)
     achieved = hop_gb / (hop_ms * 1e-3) if hop_ms > 0 else 0.0
     log("hop launches %d, mean %.2f us, %.1f GB/s" % (n_hop, hop_avg_us, achieved))

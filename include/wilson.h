@@ -195,6 +195,10 @@ wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, v
 wl_status wl_prof_enable(int32_t on);
 wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes);
 
+/* Restrict that timing to hop launches of one storage precision (a wl_prec),
+ * or -1 for all (the default). */
+wl_status wl_prof_select(int32_t prec);
+
 /* Algorithmic bytes per output site of one single-parity hop launch for a
  * storage precision, compression and RHS count: 8 links shared by the nrhs
  * right-hand sides, plus one input and one output spinor per RHS. */

@@ -298,7 +298,7 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
 
 // One block per vector: fixed-order sum of the vector's partials, then the
 // finishing step (scalar update) of the reduction kind.
-__global__ __launch_bounds__(256) void k_red_finalize(RedSpec r, const VecDesc *vec, const int32_t *active)
+__global__ __launch_bounds__(1024) void k_red_finalize(RedSpec r, const VecDesc *vec, const int32_t *active)
 {
     const int v = blockIdx.x;
     if (active && !active[v]) return;
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_red_finalize(RedSpec r, const VecDesc *
 
 hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_red_finalize, dim3(nvec), dim3(256), 0, s, r, vec, active);
+    hipLaunchKernelGGL(k_red_finalize, dim3(nvec), dim3(1024), 0, s, r, vec, active);
     return hipGetLastError();
 }
 

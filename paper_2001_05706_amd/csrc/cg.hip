@@ -129,11 +129,13 @@ struct Cg {
         return WL_OK;
     }
 
-    // rh = b' - M xh in FP64 with |rh|^2 into SC_RR
+    // rh = b' - M xh in FP64 with |rh|^2 into SC_RR.  Links are rebuilt from 12
+    // reals when the caller chose recon-12 (exact to rounding for SU(3)); the
+    // final true residual always uses all 18.
     wl_status residual64(bool use_active = true)
     {
-        WL_TRY(hop(S, P_F64, 18, false, 1, t64, xh, epi(c_plain), no_red(), s, use_active));
-        WL_TRY(hop(S, P_F64, 18, false, 0, rh, t64, epi(c_res, 2, xh, bp),
+        WL_TRY(hop(S, P_F64, recon, false, 1, t64, xh, epi(c_plain), no_red(), s, use_active));
+        WL_TRY(hop(S, P_F64, recon, false, 0, rh, t64, epi(c_res, 2, xh, bp),
                    red_spec(S, RED_STORE, S.scal(SC_RR)), s, use_active));
         return WL_OK;
     }
@@ -357,6 +359,10 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
         auto kfrac = [&]() { return cg.sloppy == P_F16 || cg.sloppy == P_BF16 ? 0.6 : 1.0; };
         std::vector<double> rmin(nv);
         for (int v = 0; v < nv; ++v) rmin[v] = rmax[v];
+        // iterations since the last update and length of the last full interval:
+        // a recurrence that crawls far beyond its usual interval has lost its way
+        std::vector<int> since(nv, 0), interval(nv, 8), crawl(nv, 0);
+        std::vector<double> rsloppy(nv, 0.0);  // sloppy |r| at the end of the last chunk
         // raise the sloppy precision one step; p is converted (restarted vectors overwrite it)
         // `folded` marks the vectors whose sloppy solution is already in the FP64
         // accumulator with a fresh FP64 residual; the others are folded in here first
@@ -424,6 +430,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     }
                     if (j == 0) rfirst = r;
                     rlast = r;
+                    rsloppy[v] = r;
                     rlow = std::min(rlow, r);
                     if (r <= target[v] || r < delta * rmax[v]) upd[v] = 1;
                 }
@@ -435,10 +442,14 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     if (rlow >= rmin[v]) upd[v] = 1;  // no progress over a whole chunk
                     rmin[v] = std::min(rmin[v], rlow);
                     if (rfirst > 0 && rlast > 0 && k > 1) {
-                        rate += std::log10(rfirst / rlast) / (k - 1);
-                        ++nrate;
+                        // fastest convergence among the vectors sets the pace
+                        rate = std::max(rate, std::log10(rfirst / rlast) / (k - 1));
+                        nrate = 1;
                     }
                 }
+                since[v] += k;
+                crawl[v] = !upd[v] && since[v] > std::max(3 * interval[v], 24);
+                if (crawl[v]) upd[v] = 1;
                 if (iters[v] >= maxiter) upd[v] = 1;
                 anyupd = anyupd || upd[v];
             }
@@ -476,9 +487,22 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     } else if (iters[v] >= maxiter) {
                         done[v] = 1;
                     } else if (!restart[v]) {
-                        stall[v] = r > 0.5 * last_true[v] ? stall[v] + 1 : 0;
+                        // no halving of the FP64 residual, or a crawl: the search
+                        // direction is stale -- restart it; a second one in a row
+                        // raises the sloppy precision
+                        if (r > 0.5 * last_true[v] || crawl[v]) {
+                            ++stall[v];
+                            restart[v] = 1;
+                        } else {
+                            stall[v] = 0;
+                        }
+                        // the recurrence drifted from the true residual: p no longer
+                        // fits the new residual, so the direction restarts
+                        if (rsloppy[v] > 0 && (r > 1.1 * rsloppy[v] || r < rsloppy[v] / 1.1)) restart[v] = 1;
                         if (stall[v] >= 2) stalled = true;
                     }
+                    if (!crawl[v] && since[v] > 0) interval[v] = since[v];
+                    since[v] = 0;
                     last_true[v] = r;
                     rmax[v] = rmin[v] = r;
                 }
@@ -487,10 +511,12 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 if ((stalled || anybad) && cg.sloppy != P_F64) {
                     WL_TRY(escalate(anybad ? "non-finite sloppy iterate" : "stagnation", upd));
                     WL_HIP(hipMemsetAsync(S.bad, 0, sizeof(int32_t) * nv, s));
+                    // every vector restarts its search direction in the new precision
                     for (int v = 0; v < nv; ++v)
                         if (!done[v]) {
-                            upd[v] = 1;
+                            upd[v] = restart[v] = 1;
                             stall[v] = 0;
+                            since[v] = 0;
                         }
                 }
                 std::vector<int> cont(nv, 0), rst(nv, 0);

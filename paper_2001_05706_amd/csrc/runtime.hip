@@ -133,6 +133,13 @@ static std::map<std::string, int> g_tuned;
 int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream_t s,
                 const std::function<hipError_t(int)> &run)
 {
+    // WL_TUNE_FORCE=<config> pins every hop launch to one candidate (tests of each variant)
+    const char *force = getenv("WL_TUNE_FORCE");
+    if (force && key.compare(0, 4, "hop/") == 0) {
+        const int c = atoi(force);
+        for (int x : cands)
+            if (x == c) return c;
+    }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
@@ -538,7 +545,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
     const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active);
     g_bytes_acc += bytes;
     Prof &P = prof();
-    const bool timed = P.on && !capturing(s);
+    const bool timed = P.on && (P.prec < 0 || P.prec == prec) && !capturing(s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         WL_HIP(hipEventCreate(&e0));
@@ -800,6 +807,14 @@ wl_status wl_prof_enable(int32_t on)
     clear_error();
     Prof &P = prof();
     P.on = on != 0;
+    return WL_OK;
+}
+
+wl_status wl_prof_select(int32_t prec)
+{
+    clear_error();
+    if (prec < -1 || prec > P_BF16) return set_error(WL_ERR_ARG, "prec must be -1 (all) or a wl_prec");
+    prof().prec = prec;
     return WL_OK;
 }
 

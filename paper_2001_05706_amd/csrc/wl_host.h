@@ -166,6 +166,7 @@ std::vector<int> hop_candidates();
 
 struct Prof {
     bool on = false;
+    int prec = -1;  // storage precision of the hops timed (-1: all)
     int64_t launches = 0;
     double ms = 0.0;
     double gbytes = 0.0;

@@ -69,6 +69,7 @@ SIGNATURES = [
     ("wl_bench_dslash", _i32, [_P, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_d), _P]),
     ("wl_bench_copy", _i32, [_i64, _i32, ctypes.POINTER(_d), _P]),
     ("wl_prof_enable", _i32, [_i32]),
+    ("wl_prof_select", _i32, [_i32]),
     ("wl_prof_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     ("wl_hop_bytes_per_site", _d, [_i32, _i32, _i32]),
 ]
@@ -234,6 +235,10 @@ def wl_bench_copy(nbytes, reps=20, stream=None) -> float:
 
 def wl_prof_enable(on=True):
     _check(lib().wl_prof_enable(int(bool(on))))
+
+
+def wl_prof_select(prec=-1):
+    _check(lib().wl_prof_select(-1 if prec == -1 else _prec(prec)))
 
 
 def wl_prof_read():

@@ -4,10 +4,13 @@ FP64 oracle, through the C ABI, for every storage precision and compression.
 Gates (relative to the oracle on the same, storage-rounded inputs):
   FP64: relative L2 error <= 1e-13
   FP32 (recon 18 or 12): <= 1e-6
-  FP16 / BF16 (recon 12, per-site norm): the only extra error is the rounding
-  of the output to storage, at most half a unit in the last place of the
-  site-normalised value: <= 2^-11 (FP16) / 2^-8 (BF16) of the site maximum,
-  plus 1e-5 for the FP32 arithmetic.
+  FP16 / BF16 (recon 12, per-site norm): compared with the oracle on the
+  inputs rounded to storage by a host model; the extra error is the rounding
+  of the output to storage (at most half a unit in the last place of the
+  site-normalised value: 2^-11 for FP16, 2^-8 for BF16, of the site maximum)
+  plus rare one-unit differences of the input rounding where the host model's
+  FP32 value sits on a rounding boundary, plus 1e-5 for the FP32 arithmetic:
+  gate 2 x 2^-11 (FP16) / 2 x 2^-8 (BF16) + 1e-5.
 """
 import numpy as np
 import pytest
@@ -19,7 +22,7 @@ from tests.gpu_util import from_dev, need_gpu, quantize_links, quantize_spinor, 
 pytestmark = pytest.mark.gpu
 
 GATE = {"f64": 1e-13, "f32": 1e-6}
-QGATE = {"f16": 2.0 ** -11 * 1.01 + 1e-5, "bf16": 2.0 ** -8 * 1.01 + 1e-5}
+QGATE = {"f16": 2.0 * 2.0 ** -11 + 1e-5, "bf16": 2.0 * 2.0 ** -8 + 1e-5}
 CASES = [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]
 
 

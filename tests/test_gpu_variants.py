@@ -1,0 +1,53 @@
+"""Every launch variant the autotuner may pick for the hop (direction fence,
+occupancy target, non-temporal or cached links) x block size, pinned one at a
+time, must give the oracle's D-slash and a converging mixed-precision solve."""
+import os
+
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+import oracle
+from tests.gpu_util import from_dev, need_gpu, to_dev
+from tests.test_gpu_dslash import CASES, check, expected, run_dslash
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def force(monkeypatch):
+    def set_cfg(var, block):
+        monkeypatch.setenv("WL_TUNE_FORCE", str(var * 1024 + block))
+    return set_cfg
+
+
+@pytest.mark.parametrize("var", [0, 1, 2, 3])
+@pytest.mark.parametrize("block", [64, 512])
+def test_every_hop_variant_matches_oracle(var, block, force):
+    w = need_gpu()
+    force(var, block)
+    L = (4, 6, 2, 8)
+    U = li.haar_links(L, 41)
+    psi = li.gaussian_spinor(L, 42, nrhs=3)
+    for prec, recon in CASES:
+        for parity, dagger in [(0, 0), (1, 1), (-1, 0), (-1, 1)]:
+            got = run_dslash(w, L, U, psi, 0.13, parity, dagger, prec, recon)
+            check(prec, got, expected(L, U, psi, 0.13, parity, dagger, prec, recon))
+
+
+@pytest.mark.parametrize("var", [0, 1, 2, 3])
+@pytest.mark.parametrize("sloppy", ["f16", "bf16"])
+def test_every_hop_variant_solves(var, sloppy, force):
+    w = need_gpu()
+    force(var, 256)
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2002)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.wilson_cg(g, to_dev(eta), x, 1, 0.1245, 1e-10, 2000, sloppy, 12, 0.1, check=False)
+    psi = from_dev(x, eta.shape)
+    g.close()
+    r = eta - oracle.wilson(L, U, psi, 0.1245)
+    tr = np.linalg.norm(r) / np.linalg.norm(eta)
+    assert st == w.WL_OK and tr <= 1e-10, (var, sloppy, st, info, tr)
