@@ -19,6 +19,8 @@ the textbook forms, each convention one of the readings in the design notes):
     the overlap operator inverted by GWU-code (Sections 1 and 3)
   * cg_eo         -- even-odd CG on the normal equations
   * sign_cheb     -- degree-d Chebyshev approximation of eps(H_W)
+  * overlap       -- D_ov(m) = (rho + m/2) + (rho - m/2) g5 eps(H_W), the
+    overlap operator, and overlap_cg, its CG solve on the normal equations
 """
 from __future__ import annotations
 
@@ -70,6 +72,9 @@ def _load():
         lib.or_sign_cheb.argtypes = [P, i32, P, P, P, i32, d, i32, d, d, d]
         lib.or_hw2_lmax.argtypes = [P, i32, P, d, P, i32]
         lib.or_hw2_lmax.restype = d
+        lib.or_overlap.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, i32]
+        lib.or_overlap_cg.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, d, i32, P, P]
+        lib.or_overlap_cg.restype = i32
         lib.or_num_threads.restype = i32
         _lib = lib
         return lib
@@ -199,3 +204,36 @@ def hw2_lmax(L, U, rho: float, v0, iters: int = 200, antiperiodic_t: bool = True
     U = _links(U, V)
     a = _field(v0, V)[0].copy()
     return float(_load().or_hw2_lmax(_p(L), int(antiperiodic_t), _p(U), float(rho), _p(a), int(iters)))
+
+
+def overlap(L, U, psi, rho: float, mass: float, degree: int, lo: float, hi: float, scale: float,
+            dagger: bool = False, antiperiodic_t: bool = True):
+    """D_ov(m) psi = (rho + m/2) psi + (rho - m/2) g5 eps(H_W) psi (dagger: eps g5)."""
+    L = _dims(L)
+    V = int(np.prod(L))
+    U = _links(U, V)
+    a = _field(psi, V)
+    out = np.empty_like(a)
+    _load().or_overlap(_p(L), int(antiperiodic_t), _p(U), _p(a), _p(out), a.shape[0], float(rho), float(mass),
+                       int(degree), float(lo), float(hi), float(scale), int(dagger))
+    return out.reshape(np.shape(psi))
+
+
+def overlap_cg(L, U, eta, rho: float, mass: float, degree: int, lo: float, hi: float, scale: float, tol: float,
+               maxiter: int = 10000, x0=None, antiperiodic_t: bool = True):
+    """Solve D_ov(m) psi = eta by CGNR with the Chebyshev sign function.
+
+    Returns (psi, converged, iters[nrhs], resid[nrhs]), resid = |eta - D_ov psi| / |eta|.
+    """
+    L = _dims(L)
+    V = int(np.prod(L))
+    U = _links(U, V)
+    e = _field(eta, V)
+    x = np.zeros_like(e) if x0 is None else _field(x0, V).copy()
+    nrhs = e.shape[0]
+    iters = np.zeros(nrhs, dtype=np.int32)
+    res = np.zeros(nrhs, dtype=np.float64)
+    st = _load().or_overlap_cg(_p(L), int(antiperiodic_t), _p(U), _p(e), _p(x), nrhs, float(rho), float(mass),
+                               int(degree), float(lo), float(hi), float(scale), float(tol), int(maxiter),
+                               _p(iters), _p(res))
+    return x.reshape(np.shape(eta)), st == 0, iters, res

@@ -1,7 +1,7 @@
 /*
  * wilson_oracle.c -- plain, slow FP64 CPU reference for the Wilson-Dirac
  * inverter path (dslash, even-odd CG on the normal equations, Chebyshev
- * sign function).
+ * sign function, overlap operator and its CG solve).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
  * includes this file; only the tests, the smoke check and the CPU-baseline leg
@@ -469,6 +469,108 @@ void or_sign_cheb(const int32_t *L, int32_t antiperiodic_t, const double *U, con
         vaxpby(0.0, out, 1.0 / sqrt(scale), out, n);
     }
     free(c); free(b0); free(b1); free(b2); free(w); free(yb);
+}
+
+/* ---- overlap operator (GWU-code's inverter, Sections 1 and 3) ----------- */
+/* Neuberger's overlap operator with bare mass m, built on the approximate
+ * sign function above:
+ *   D_ov(m) = (rho + m/2) + (rho - m/2) g5 eps(H_W)
+ *   D_ov(m)^dagger = (rho + m/2) + (rho - m/2) eps(H_W) g5      (eps is Hermitian)
+ * whole lattice, nrhs fields. */
+void or_overlap(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
+                double *out_, int32_t nrhs, double rho, double mass, int32_t degree, double lo,
+                double hi, double scale, int32_t dagger)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    const double a = rho + 0.5 * mass, b = rho - 0.5 * mass;
+    cplx *t = malloc(sizeof(cplx) * n), *w = malloc(sizeof(cplx) * n);
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *v = (const cplx *)in_ + (size_t)r * n;
+        cplx *out = (cplx *)out_ + (size_t)r * n;
+        if (dagger) {
+            vgamma5(v, t, g.V);
+            or_sign_cheb(L, antiperiodic_t, U, (const double *)t, (double *)w, 1, rho, degree, lo, hi, scale);
+        } else {
+            or_sign_cheb(L, antiperiodic_t, U, (const double *)v, (double *)t, 1, rho, degree, lo, hi, scale);
+            vgamma5(t, w, g.V);
+        }
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) out[i] = a * v[i] + b * w[i];
+    }
+    free(t); free(w);
+}
+
+/* Overlap solve D_ov(m) x = eta by CG on the normal equations (CGNR), tracking
+ * the residual rt = eta - D x of the original system:
+ *   rt = eta - D x;  s = D^dagger rt;  p = s;  gamma = |s|^2
+ *   repeat:  q = D p;  alpha = gamma / |q|^2;  x += alpha p;  rt -= alpha q;
+ *            stop when |rt| <= tol |eta| holds for the recomputed rt;
+ *            s = D^dagger rt;  p = s + (|s|^2 / gamma) p
+ * x holds the initial guess on entry.  Returns 0 when every system converged.
+ * resid_out: |eta - D x| / |eta| with the same operator, recomputed. */
+int32_t or_overlap_cg(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *eta_,
+                      double *x_, int32_t nrhs, double rho, double mass, int32_t degree, double lo,
+                      double hi, double scale, double tol, int32_t maxiter, int32_t *iters_out,
+                      double *resid_out)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    cplx *rt = malloc(sizeof(cplx) * n), *sv = malloc(sizeof(cplx) * n);
+    cplx *p = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
+    int32_t status = 0;
+#define OV_APPLY(in, out, dag) \
+    or_overlap(L, antiperiodic_t, U, (const double *)(in), (double *)(out), 1, rho, mass, degree, lo, hi, scale, dag)
+    for (int rh = 0; rh < nrhs; ++rh) {
+        const cplx *eta = (const cplx *)eta_ + (size_t)rh * n;
+        cplx *x = (cplx *)x_ + (size_t)rh * n;
+        double eta_norm = sqrt(vnorm2(eta, n));
+        int it = 0, converged = 0;
+        if (eta_norm == 0.0) {
+            memset(x, 0, sizeof(cplx) * n);
+            iters_out[rh] = 0;
+            resid_out[rh] = 0.0;
+            continue;
+        }
+        OV_APPLY(x, q, 0);
+        memcpy(rt, eta, sizeof(cplx) * n);
+        vaxpby(-1.0, q, 1.0, rt, n);
+        OV_APPLY(rt, sv, 1);
+        memcpy(p, sv, sizeof(cplx) * n);
+        double gam = vnorm2(sv, n);
+        while (it < maxiter) {
+            if (sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+                OV_APPLY(x, q, 0);
+                memcpy(rt, eta, sizeof(cplx) * n);
+                vaxpby(-1.0, q, 1.0, rt, n);
+                if (sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+                    converged = 1;
+                    break;
+                }
+                OV_APPLY(rt, sv, 1);
+                gam = vnorm2(sv, n);
+                memcpy(p, sv, sizeof(cplx) * n);
+            }
+            OV_APPLY(p, q, 0);
+            double alpha = gam / vnorm2(q, n);
+            vaxpby(alpha, p, 1.0, x, n);
+            vaxpby(-alpha, q, 1.0, rt, n);
+            OV_APPLY(rt, sv, 1);
+            double gam_new = vnorm2(sv, n);
+            vaxpby(1.0, sv, gam_new / gam, p, n);
+            gam = gam_new;
+            ++it;
+        }
+        OV_APPLY(x, q, 0);
+        memcpy(rt, eta, sizeof(cplx) * n);
+        vaxpby(-1.0, q, 1.0, rt, n);
+        resid_out[rh] = sqrt(vnorm2(rt, n)) / eta_norm;
+        iters_out[rh] = it;
+        if (!(converged || resid_out[rh] <= tol)) status = 1;
+    }
+#undef OV_APPLY
+    free(rt); free(sv); free(p); free(q);
+    return status;
 }
 
 /* Largest eigenvalue of H_W^2 by power iteration from the start vector v0

@@ -15,6 +15,7 @@ import pytest
 
 import lattice_inputs as li
 from tests import dense_wilson as dw
+from tests import test_oracle_overlap as ovpins
 from tests import test_oracle_pins as pins
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -50,6 +51,13 @@ MUTATIONS = [
     ("Clenshaw final half of c0 (operator)", "w[i] = yb[i] - b2[i] + 0.5 * c[0] * v[i];", "w[i] = yb[i] - b2[i] + c[0] * v[i];"),
     ("Clenshaw recurrence sign", "b0[i] = 2.0 * yb[i] - b2[i] + c[j] * v[i];", "b0[i] = 2.0 * yb[i] + b2[i] + c[j] * v[i];"),
     ("sign function scale exponent", "1.0 / sqrt(scale), out, n);", "1.0 / scale, out, n);"),
+    ("overlap mass enters both terms with one sign", "b = rho - 0.5 * mass;", "b = rho + 0.5 * mass;"),
+    ("overlap missing gamma5", "            vgamma5(t, w, g.V);\n", "            memcpy(w, t, sizeof(cplx) * n);\n"),
+    ("overlap adjoint equals the operator",
+     "            vgamma5(v, t, g.V);\n            or_sign_cheb(L, antiperiodic_t, U, (const double *)t, (double *)w,",
+     "            vgamma5(v, t, g.V);\n            or_sign_cheb(L, antiperiodic_t, U, (const double *)v, (double *)w,"),
+    ("overlap CG residual update sign", "            vaxpby(-alpha, q, 1.0, rt, n);\n            OV_APPLY",
+     "            vaxpby(alpha, q, 1.0, rt, n);\n            OV_APPLY"),
 ]
 
 
@@ -88,6 +96,7 @@ def small_cases():
         "dense4": (L4, U4, dw.hopping_matrix(L4, U4)),
         "rough": ((4, 2, 2, 4), U4),
         "hw": (Lh, Uh, 1.5, HW, w, vec),
+        "ov": ovpins.make_case(),
     }
 
 
@@ -104,11 +113,15 @@ def battery(cases):
     yield lambda: pins.test_dense_solve_matches_cg_eo(cases["dense4"])
     yield lambda: pins.test_chebyshev_scalar_error(0.01, 2.2e-13)
     yield lambda: pins.test_sign_function_matches_dense_sign(cases["hw"])
+    yield lambda: ovpins.test_overlap_matches_dense_exact_sign(cases["ov"], 0.25)
+    yield lambda: ovpins.test_overlap_ginsparg_wilson_and_normality(cases["ov"])
+    yield lambda: ovpins.test_overlap_cg_matches_dense_solve(cases["ov"])
 
 
 def test_unmutated_battery_passes(small_cases, tmp_path, monkeypatch):
     mod = load_mutant(tmp_path, "none", "/*", "/*")
     monkeypatch.setattr(pins, "oracle", mod)
+    monkeypatch.setattr(ovpins, "oracle", mod)
     for check in battery(small_cases):
         check()
 
@@ -117,6 +130,7 @@ def test_unmutated_battery_passes(small_cases, tmp_path, monkeypatch):
 def test_pins_catch_mutation(name, old, new, small_cases, tmp_path, monkeypatch):
     mod = load_mutant(tmp_path, name, old, new)
     monkeypatch.setattr(pins, "oracle", mod)
+    monkeypatch.setattr(ovpins, "oracle", mod)
     caught = []
     for i, check in enumerate(battery(small_cases)):
         try:
