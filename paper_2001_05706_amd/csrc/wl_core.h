@@ -218,6 +218,32 @@ WL_HD void load_spinor(const void *base, const float *norm, int stride, int cb,
     }
 }
 
+// As load_spinor, but FP16/BF16 values are returned site-normalised with the
+// site norm in *nrm (1 for FP64/FP32), so that a caller can apply the norm
+// after a linear step that shrinks the data (the hop's spin projection).
+template <int P>
+WL_HD void load_spinor_unscaled(const void *base, const float *norm, int stride, int cb,
+                                typename SpinorFmt<P>::real v[24], typename SpinorFmt<P>::real *nrm)
+{
+    using CH = typename SpinorFmt<P>::chunk;
+    if constexpr (P == P_F64 || P == P_F32) {
+        load_spinor<P>(base, norm, stride, cb, v);
+        *nrm = 1;
+    } else {
+        *nrm = *row_elem<float>(norm, 0, 0, cb);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uint4 w = *row_elem<CH>(base, c, stride, cb);
+            uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[8 * c + 2 * k] = lo16_to_float<P>(q[k]);
+                v[8 * c + 2 * k + 1] = hi16_to_float<P>(q[k]);
+            }
+        }
+    }
+}
+
 template <int P>
 WL_HD void store_spinor(void *base, float *norm, int stride, int cb, const typename SpinorFmt<P>::real v[24])
 {
@@ -473,13 +499,21 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
     }
     const int ncb = (nx >> 1) + d.Lxh * (ny + d.L[1] * (nz + d.L[2] * nt));
 
-    T v[24];
-    load_spinor<SP>(a.in, a.in_norm, a.stride, ncb, v);
+    T v[24], nrm;
+    load_spinor_unscaled<SP>(a.in, a.in_norm, a.stride, ncb, v, &nrm);
     // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
     constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
     cpx<T> h0[3], h1[3];
     project<MU, SG>(v, h0, h1);
-    if (flip) {
+    if constexpr (SP == P_F16 || SP == P_BF16) {
+        // site norm of the half-precision neighbour and the boundary sign, on 12 values
+        const T f = flip ? -nrm : nrm;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            h0[c] = {f * h0[c].re, f * h0[c].im};
+            h1[c] = {f * h1[c].re, f * h1[c].im};
+        }
+    } else if (flip) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             h0[c] = {-h0[c].re, -h0[c].im};
