@@ -21,6 +21,9 @@ the textbook forms, each convention one of the readings in the design notes):
   * sign_cheb     -- degree-d Chebyshev approximation of eps(H_W)
   * overlap       -- D_ov(m) = (rho + m/2) + (rho - m/2) g5 eps(H_W), the
     overlap operator, and overlap_cg, its CG solve on the normal equations
+  * clover / wilson_clover / cg_eo_clover -- the Sheikholeslami-Wohlert
+    clover term A (QUDA_DIRAC_CLOVER, Table 1), D_k = A - kappa H, and its
+    even-odd CGNR on the asymmetric Schur complement
 """
 from __future__ import annotations
 
@@ -75,6 +78,10 @@ def _load():
         lib.or_overlap.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, i32]
         lib.or_overlap_cg.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, d, i32, P, P]
         lib.or_overlap_cg.restype = i32
+        lib.or_clover.argtypes = [P, P, d, d, P]
+        lib.or_wilson_clover.argtypes = [P, i32, P, P, P, i32, d, d, i32]
+        lib.or_cg_eo_clover.argtypes = [P, i32, P, P, P, i32, d, d, d, i32, P, P]
+        lib.or_cg_eo_clover.restype = i32
         lib.or_num_threads.restype = i32
         _lib = lib
         return lib
@@ -236,4 +243,45 @@ def overlap_cg(L, U, eta, rho: float, mass: float, degree: int, lo: float, hi: f
     st = _load().or_overlap_cg(_p(L), int(antiperiodic_t), _p(U), _p(e), _p(x), nrhs, float(rho), float(mass),
                                int(degree), float(lo), float(hi), float(scale), float(tol), int(maxiter),
                                _p(iters), _p(res))
+    return x.reshape(np.shape(eta)), st == 0, iters, res
+
+
+def clover(L, U, kappa: float, csw: float) -> np.ndarray:
+    """A(x) = 1 + i kappa c_sw sum_{m<n} s_mn F_mn(x) per site: shape (V, 12, 12),
+    row/column index 3 * spin + colour."""
+    L = _dims(L)
+    V = int(np.prod(L))
+    U = _links(U, V)
+    out = np.zeros((V, 12, 12), dtype=np.complex128)
+    _load().or_clover(_p(L), _p(U), float(kappa), float(csw), _p(out))
+    return out
+
+
+def wilson_clover(L, U, psi, kappa: float, csw: float, dagger: bool = False, antiperiodic_t: bool = True):
+    """D_k psi = A psi - kappa H psi (dagger: A psi - kappa H^dagger psi), whole lattice."""
+    L = _dims(L)
+    V = int(np.prod(L))
+    U = _links(U, V)
+    a = _field(psi, V)
+    out = np.empty_like(a)
+    _load().or_wilson_clover(_p(L), int(antiperiodic_t), _p(U), _p(a), _p(out), a.shape[0], float(kappa),
+                             float(csw), int(dagger))
+    return out.reshape(np.shape(psi))
+
+
+def cg_eo_clover(L, U, eta, kappa: float, csw: float, tol: float, maxiter: int = 10000, x0=None,
+                 antiperiodic_t: bool = True):
+    """Solve (A - kappa H) psi = eta by even-odd CGNR on A_ee - kappa^2 D_eo A_oo^-1 D_oe.
+
+    Returns (psi, converged, iters[nrhs], true_resid[nrhs]) as cg_eo."""
+    L = _dims(L)
+    V = int(np.prod(L))
+    U = _links(U, V)
+    e = _field(eta, V)
+    x = np.zeros_like(e) if x0 is None else _field(x0, V).copy()
+    nrhs = e.shape[0]
+    iters = np.zeros(nrhs, dtype=np.int32)
+    res = np.zeros(nrhs, dtype=np.float64)
+    st = _load().or_cg_eo_clover(_p(L), int(antiperiodic_t), _p(U), _p(e), _p(x), nrhs, float(kappa), float(csw),
+                                 float(tol), int(maxiter), _p(iters), _p(res))
     return x.reshape(np.shape(eta)), st == 0, iters, res

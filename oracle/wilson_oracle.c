@@ -1,7 +1,7 @@
 /*
  * wilson_oracle.c -- plain, slow FP64 CPU reference for the Wilson-Dirac
  * inverter path (dslash, even-odd CG on the normal equations, Chebyshev
- * sign function, overlap operator and its CG solve).
+ * sign function, overlap operator and its CG solve, clover term).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
  * includes this file; only the tests, the smoke check and the CPU-baseline leg
@@ -594,6 +594,290 @@ double or_hw2_lmax(const int32_t *L, int32_t antiperiodic_t, const double *U, do
     }
     free(v); free(w); free(u);
     return lam;
+}
+
+/* ---- clover term (QUDA_DIRAC_CLOVER of Table 1) ------------------------ */
+/* Sheikholeslami-Wohlert term in the normalisation of the hopping term above
+ * (forward hop 1 - g_mu), with the clover-leaf field strength:
+ *   Q_mn(x) = sum of the four plaquettes of the m-n plane that start and end
+ *             at x, each traversed m-direction first (counter-clockwise)
+ *   F_mn(x) = (Q_mn(x) - Q_mn(x)^dagger) / 8            (anti-Hermitian)
+ *   s_mn    = (i/2) [g_m, g_n]
+ *   D_mass  = (4 + m0) - H/2 + (i c_sw / 2) sum_{m<n} s_mn F_mn
+ *   D_k     = 2 kappa D_mass = A - kappa H,  A(x) = 1 + i kappa c_sw sum_{m<n} s_mn F_mn(x)
+ * A(x) is a Hermitian 12 x 12 matrix at each site (spin-major, colour-minor),
+ * stored as A[s][12][12] complex.  Gauge links are periodic in every
+ * direction; the fermion boundary factor of the hop does not enter Q. */
+
+/* c = op(a) op(b) for 3x3 complex matrices, op = dagger when the flag is set */
+static void m3_mul(const cplx *a, int ad, const cplx *b, int bd, cplx *c)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx v = 0;
+            for (int k = 0; k < 3; ++k) {
+                cplx x = ad ? conj(a[k * 3 + i]) : a[i * 3 + k];
+                cplx y = bd ? conj(b[j * 3 + k]) : b[k * 3 + j];
+                v += x * y;
+            }
+            c[i * 3 + j] = v;
+        }
+}
+
+/* product of four links W1 W2 W3 W4, each with its own dagger flag */
+static void m3_loop(const cplx *w[4], const int d[4], cplx *out)
+{
+    cplx t1[9], t2[9];
+    m3_mul(w[0], d[0], w[1], d[1], t1);
+    m3_mul(t1, 0, w[2], d[2], t2);
+    m3_mul(t2, 0, w[3], d[3], out);
+}
+
+/* site index of c + a m + b n with periodic wrap */
+static long shifted(const lattice *g, const int c[4], int m, int a, int n, int b)
+{
+    int y[4] = {c[0], c[1], c[2], c[3]};
+    y[m] = ((y[m] + a) % g->L[m] + g->L[m]) % g->L[m];
+    y[n] = ((y[n] + b) % g->L[n] + g->L[n]) % g->L[n];
+    return site_index(g, y);
+}
+
+static void field_strength(const lattice *g, const cplx *U, long s, int m, int n, cplx F[9])
+{
+    int c[4];
+    site_coords(g, s, c);
+#define LK(site, dir) (U + ((site) * 4 + (dir)) * 9)
+    const long xm = shifted(g, c, m, 1, n, 0), xn = shifted(g, c, m, 0, n, 1);
+    const long xmm = shifted(g, c, m, -1, n, 0), xnm = shifted(g, c, m, 0, n, -1);
+    const long xmm_np = shifted(g, c, m, -1, n, 1), xmm_nm = shifted(g, c, m, -1, n, -1);
+    const long xmp_nm = shifted(g, c, m, 1, n, -1);
+    cplx Q[9] = {0}, leaf[9];
+    /* x -> x+m -> x+m+n -> x+n -> x */
+    const cplx *w1[4] = {LK(s, m), LK(xm, n), LK(xn, m), LK(s, n)};
+    const int d1[4] = {0, 0, 1, 1};
+    /* x -> x+n -> x+n-m -> x-m -> x */
+    const cplx *w2[4] = {LK(s, n), LK(xmm_np, m), LK(xmm, n), LK(xmm, m)};
+    const int d2[4] = {0, 1, 1, 0};
+    /* x -> x-m -> x-m-n -> x-n -> x */
+    const cplx *w3[4] = {LK(xmm, m), LK(xmm_nm, n), LK(xmm_nm, m), LK(xnm, n)};
+    const int d3[4] = {1, 1, 0, 0};
+    /* x -> x-n -> x-n+m -> x+m -> x */
+    const cplx *w4[4] = {LK(xnm, n), LK(xnm, m), LK(xmp_nm, n), LK(s, m)};
+    const int d4[4] = {1, 0, 0, 1};
+#undef LK
+    const cplx **ws[4] = {w1, w2, w3, w4};
+    const int *ds[4] = {d1, d2, d3, d4};
+    for (int l = 0; l < 4; ++l) {
+        m3_loop(ws[l], ds[l], leaf);
+        for (int k = 0; k < 9; ++k) Q[k] += leaf[k];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) F[i * 3 + j] = (Q[i * 3 + j] - conj(Q[j * 3 + i])) / 8.0;
+}
+
+/* A(x) for every site: A_ out[V][12][12] complex */
+void or_clover(const int32_t *L, const double *U_, double kappa, double csw, double *A_)
+{
+    lattice g = make_lattice(L, 0);
+    const cplx *U = (const cplx *)U_;
+    cplx *A = (cplx *)A_;
+    cplx gm[4][4][4], sig[4][4][4][4];
+    for (int mu = 0; mu < 4; ++mu) gamma_matrix(mu, gm[mu]);
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n)
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    cplx v = 0;
+                    for (int k = 0; k < 4; ++k) v += gm[m][i][k] * gm[n][k][j] - gm[n][i][k] * gm[m][k][j];
+                    sig[m][n][i][j] = 0.5 * I * v;
+                }
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g.V; ++s) {
+        cplx *a = A + s * 144;
+        for (int k = 0; k < 144; ++k) a[k] = 0;
+        for (int k = 0; k < 12; ++k) a[k * 12 + k] = 1;
+        for (int m = 0; m < 4; ++m)
+            for (int n = m + 1; n < 4; ++n) {
+                cplx F[9];
+                field_strength(&g, U, s, m, n, F);
+                for (int i = 0; i < 4; ++i)
+                    for (int j = 0; j < 4; ++j)
+                        for (int aa = 0; aa < 3; ++aa)
+                            for (int bb = 0; bb < 3; ++bb)
+                                a[(i * 3 + aa) * 12 + j * 3 + bb] += I * kappa * csw * sig[m][n][i][j] * F[aa * 3 + bb];
+            }
+    }
+}
+
+/* inverse of a 12 x 12 complex matrix by Gauss-Jordan elimination with
+ * partial pivoting; returns 0 on success */
+static int inv12(const cplx *a, cplx *out)
+{
+    cplx m[12][24];
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 24; ++j) m[i][j] = j < 12 ? a[i * 12 + j] : (j - 12 == i ? 1.0 : 0.0);
+    for (int col = 0; col < 12; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 12; ++r)
+            if (cabs(m[r][col]) > cabs(m[piv][col])) piv = r;
+        if (cabs(m[piv][col]) == 0.0) return 1;
+        if (piv != col)
+            for (int j = 0; j < 24; ++j) {
+                cplx t = m[col][j];
+                m[col][j] = m[piv][j];
+                m[piv][j] = t;
+            }
+        cplx d = m[col][col];
+        for (int j = 0; j < 24; ++j) m[col][j] /= d;
+        for (int r = 0; r < 12; ++r)
+            if (r != col && m[r][col] != 0) {
+                cplx f = m[r][col];
+                for (int j = 0; j < 24; ++j) m[r][j] -= f * m[col][j];
+            }
+    }
+    for (int i = 0; i < 12; ++i)
+        for (int j = 0; j < 12; ++j) out[i * 12 + j] = m[i][j + 12];
+    return 0;
+}
+
+/* out_s = M_s in_s at the sites of the given parity (-1: all); other sites 0 */
+static void apply_site_matrix(const lattice *g, const cplx *M, const cplx *in, cplx *out, int parity)
+{
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < g->V; ++s) {
+        int c[4];
+        site_coords(g, s, c);
+        if (parity >= 0 && site_parity(c) != parity) {
+            for (int k = 0; k < 12; ++k) out[s * 12 + k] = 0;
+            continue;
+        }
+        for (int i = 0; i < 12; ++i) {
+            cplx v = 0;
+            for (int j = 0; j < 12; ++j) v += M[s * 144 + i * 12 + j] * in[s * 12 + j];
+            out[s * 12 + i] = v;
+        }
+    }
+}
+
+/* out = D_k in = A in - kappa H in (dagger: A in - kappa H^dagger in), whole lattice */
+void or_wilson_clover(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
+                      double *out_, int32_t nrhs, double kappa, double csw, int32_t dagger)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    cplx *A = malloc(sizeof(cplx) * 144 * g.V), *t = malloc(sizeof(cplx) * n);
+    or_clover(L, U, kappa, csw, (double *)A);
+    or_hop(L, antiperiodic_t, U, in_, out_, nrhs, -1, dagger);
+    for (int r = 0; r < nrhs; ++r) {
+        const cplx *in = (const cplx *)in_ + (size_t)r * n;
+        cplx *out = (cplx *)out_ + (size_t)r * n;
+        apply_site_matrix(&g, A, in, t, -1);
+        vaxpby(1.0, t, -kappa, out, n);
+    }
+    free(A); free(t);
+}
+
+/* Even-odd CGNR for the clover operator, on the asymmetric Schur complement
+ *   M = A_ee - kappa^2 D_eo A_oo^{-1} D_oe,  M^dagger = A_ee - kappa^2 D_oe^dagger A_oo^{-1} D_eo^dagger
+ *   b' = eta_e + kappa D_eo A_oo^{-1} eta_o;   psi_o = A_oo^{-1} (eta_o + kappa D_oe psi_e)
+ * with the same recurrence, stop test and outputs as or_cg_eo. */
+int32_t or_cg_eo_clover(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *eta_,
+                        double *x_, int32_t nrhs, double kappa, double csw, double tol, int32_t maxiter,
+                        int32_t *iters_out, double *resid_out)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long V = g.V, n = V * 12;
+    cplx *A = malloc(sizeof(cplx) * 144 * V), *Ai = malloc(sizeof(cplx) * 144 * V);
+    cplx *bp = malloc(sizeof(cplx) * n), *rt = malloc(sizeof(cplx) * n);
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *q = malloc(sizeof(cplx) * n), *t1 = malloc(sizeof(cplx) * n), *t2 = malloc(sizeof(cplx) * n);
+    int32_t status = 0;
+    or_clover(L, U, kappa, csw, (double *)A);
+    for (long s = 0; s < V; ++s)
+        if (inv12(A + s * 144, Ai + s * 144)) status = 1;
+    /* out = M in (dagger: M^dagger in) on even-site vectors */
+#define CLOV_SCHUR(in, out, dag)                                                                  \
+    do {                                                                                          \
+        or_hop(L, antiperiodic_t, U, (const double *)(in), (double *)t1, 1, 1, (dag));           \
+        apply_site_matrix(&g, Ai, t1, t2, 1);                                                     \
+        or_hop(L, antiperiodic_t, U, (const double *)t2, (double *)(out), 1, 0, (dag));          \
+        apply_site_matrix(&g, A, (in), t1, 0);                                                    \
+        vaxpby(1.0, t1, -kappa * kappa, (out), n);                                                \
+    } while (0)
+
+    for (int rh = 0; rh < nrhs && status == 0; ++rh) {
+        const cplx *eta = (const cplx *)eta_ + (size_t)rh * n;
+        cplx *x = (cplx *)x_ + (size_t)rh * n;
+        double eta_norm = sqrt(vnorm2(eta, n));
+        int it = 0, converged = 0;
+        /* b' = eta_e + kappa D_eo A_oo^{-1} eta_o */
+        apply_site_matrix(&g, Ai, eta, t1, 1);
+        or_hop(L, antiperiodic_t, U, (const double *)t1, (double *)bp, 1, 0, 0);
+        vaxpby(1.0, eta, kappa, bp, n);
+        vzero_parity(&g, bp, 1);
+        vzero_parity(&g, x, 1);
+        if (eta_norm == 0.0) {
+            memset(x, 0, sizeof(cplx) * n);
+            iters_out[rh] = 0;
+            resid_out[rh] = 0.0;
+            continue;
+        }
+        CLOV_SCHUR(x, q, 0);
+        memcpy(rt, bp, sizeof(cplx) * n);
+        vaxpby(-1.0, q, 1.0, rt, n);
+        CLOV_SCHUR(rt, r, 1);
+        memcpy(p, r, sizeof(cplx) * n);
+        double gam = vnorm2(r, n);
+        while (it < maxiter) {
+            if (sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+                CLOV_SCHUR(x, q, 0);
+                memcpy(rt, bp, sizeof(cplx) * n);
+                vaxpby(-1.0, q, 1.0, rt, n);
+                if (sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+                    converged = 1;
+                    break;
+                }
+                CLOV_SCHUR(rt, r, 1);
+                gam = vnorm2(r, n);
+                memcpy(p, r, sizeof(cplx) * n);
+            }
+            CLOV_SCHUR(p, q, 0);
+            double alpha = gam / vnorm2(q, n);
+            vaxpby(alpha, p, 1.0, x, n);
+            vaxpby(-alpha, q, 1.0, rt, n);
+            CLOV_SCHUR(rt, r, 1);
+            double gam_new = vnorm2(r, n);
+            vaxpby(1.0, r, gam_new / gam, p, n);
+            gam = gam_new;
+            ++it;
+        }
+        if (!converged && sqrt(vnorm2(rt, n)) <= tol * eta_norm) {
+            CLOV_SCHUR(x, q, 0);
+            memcpy(rt, bp, sizeof(cplx) * n);
+            vaxpby(-1.0, q, 1.0, rt, n);
+            converged = sqrt(vnorm2(rt, n)) <= tol * eta_norm;
+        }
+        /* psi_o = A_oo^{-1} (eta_o + kappa D_oe psi_e) */
+        or_hop(L, antiperiodic_t, U, (const double *)x, (double *)t1, 1, 1, 0);
+        vaxpby(1.0, eta, kappa, t1, n);
+        apply_site_matrix(&g, Ai, t1, t2, 1);
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < V; ++s) {
+            int c[4];
+            site_coords(&g, s, c);
+            if (site_parity(c) == 1)
+                for (int k = 0; k < 12; ++k) x[s * 12 + k] = t2[s * 12 + k];
+        }
+        /* independent true residual with the whole-lattice operator */
+        or_wilson_clover(L, antiperiodic_t, U, (const double *)x, (double *)t1, 1, kappa, csw, 0);
+        vaxpby(1.0, eta, -1.0, t1, n);
+        iters_out[rh] = it;
+        resid_out[rh] = sqrt(vnorm2(t1, n)) / eta_norm;
+        if (!converged) status = 1;
+    }
+#undef CLOV_SCHUR
+    free(A); free(Ai); free(bp); free(rt); free(r); free(p); free(q); free(t1); free(t2);
+    return status;
 }
 
 /* Number of OpenMP threads the oracle runs on. */

@@ -15,6 +15,7 @@ import pytest
 
 import lattice_inputs as li
 from tests import dense_wilson as dw
+from tests import test_oracle_clover as clpins
 from tests import test_oracle_overlap as ovpins
 from tests import test_oracle_pins as pins
 
@@ -58,6 +59,18 @@ MUTATIONS = [
      "            vgamma5(v, t, g.V);\n            or_sign_cheb(L, antiperiodic_t, U, (const double *)v, (double *)w,"),
     ("overlap CG residual update sign", "            vaxpby(-alpha, q, 1.0, rt, n);\n            OV_APPLY",
      "            vaxpby(alpha, q, 1.0, rt, n);\n            OV_APPLY"),
+    ("clover leaf link not daggered", "const int d1[4] = {0, 0, 1, 1};", "const int d1[4] = {0, 0, 0, 1};"),
+    ("clover leaf through the wrong corner", "LK(xmm_nm, n), LK(xmm_nm, m), LK(xnm, n)",
+     "LK(xmm_nm, n), LK(xnm, m), LK(xnm, n)"),
+    ("clover field strength normalisation", "F[i * 3 + j] = (Q[i * 3 + j] - conj(Q[j * 3 + i])) / 8.0;",
+     "F[i * 3 + j] = (Q[i * 3 + j] - conj(Q[j * 3 + i])) / 4.0;"),
+    ("clover term sign", "+= I * kappa * csw * sig[m][n][i][j]", "-= I * kappa * csw * sig[m][n][i][j]"),
+    ("sigma commutator reversed", "v += gm[m][i][k] * gm[n][k][j] - gm[n][i][k] * gm[m][k][j];",
+     "v += gm[n][i][k] * gm[m][k][j] - gm[m][i][k] * gm[n][k][j];"),
+    ("clover Schur uses A_oo, not its inverse", "        apply_site_matrix(&g, Ai, t1, t2, 1);      ",
+     "        apply_site_matrix(&g, A, t1, t2, 1);       "),
+    ("clover source uses A_oo, not its inverse", "apply_site_matrix(&g, Ai, eta, t1, 1);",
+     "apply_site_matrix(&g, A, eta, t1, 1);"),
 ]
 
 
@@ -97,6 +110,7 @@ def small_cases():
         "rough": ((4, 2, 2, 4), U4),
         "hw": (Lh, Uh, 1.5, HW, w, vec),
         "ov": ovpins.make_case(),
+        "clover": ((4, 2, 2, 4), li.haar_links((4, 2, 2, 4), 41)),
     }
 
 
@@ -116,12 +130,17 @@ def battery(cases):
     yield lambda: ovpins.test_overlap_matches_dense_exact_sign(cases["ov"], 0.25)
     yield lambda: ovpins.test_overlap_ginsparg_wilson_and_normality(cases["ov"])
     yield lambda: ovpins.test_overlap_cg_matches_dense_solve(cases["ov"])
+    yield lambda: clpins.test_abelian_flux_closed_form(1, 2)
+    yield lambda: clpins.test_clover_hermitian_chiral_blocks(cases["clover"])
+    yield lambda: clpins.test_clover_gamma5_hermiticity_and_gauge_covariance(cases["clover"])
+    yield lambda: clpins.test_clover_cg_matches_dense_solve((2, 2, 2, 2), 43)
 
 
 def test_unmutated_battery_passes(small_cases, tmp_path, monkeypatch):
     mod = load_mutant(tmp_path, "none", "/*", "/*")
     monkeypatch.setattr(pins, "oracle", mod)
     monkeypatch.setattr(ovpins, "oracle", mod)
+    monkeypatch.setattr(clpins, "oracle", mod)
     for check in battery(small_cases):
         check()
 
@@ -131,6 +150,7 @@ def test_pins_catch_mutation(name, old, new, small_cases, tmp_path, monkeypatch)
     mod = load_mutant(tmp_path, name, old, new)
     monkeypatch.setattr(pins, "oracle", mod)
     monkeypatch.setattr(ovpins, "oracle", mod)
+    monkeypatch.setattr(clpins, "oracle", mod)
     caught = []
     for i, check in enumerate(battery(small_cases)):
         try:
