@@ -164,6 +164,39 @@ wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t n
                             int32_t degree, double lo, double hi, double scale, wl_prec prec,
                             int32_t recon, void *stream);
 
+/* ---------------------------------------------------------------- overlap operator */
+
+/* out = D_ov(m) in, the overlap operator of the GWU-code inverter (Sections 1
+ * and 3), with the sign function of overlap_sign_cheb:
+ *   D_ov(m)        = (rho + m/2) + (rho - m/2) g5 eps(H_W)
+ *   D_ov(m)^dagger = (rho + m/2) + (rho - m/2) eps(H_W) g5      (dagger != 0)
+ * Whole lattice, nrhs canonical fields (device), in and out must not overlap.
+ * mass in [0, 2 rho); degree, lo, hi, scale as for overlap_sign_cheb (scale <= 0:
+ * estimated from in's first field).  prec WL_F64 or WL_F32.  One call costs one
+ * sign-function evaluation: 2 (degree + 1) + 1 applications of H_W.
+ * Synchronises `stream`. */
+wl_status overlap_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double rho, double mass,
+                         int32_t degree, double lo, double hi, double scale, int32_t dagger, wl_prec prec,
+                         int32_t recon, void *stream);
+
+/* Solve D_ov(m) x = eta for nrhs canonical fields (device; x holds the initial
+ * guess on entry and the solution on exit; eta and x must not overlap).  CG on
+ * the normal equations with the residual of the original system tracked, in a
+ * defect-correction loop: the FP64 residual eta - D_ov x is recomputed with the
+ * FP64 operator, an inner CG in the working precision `sloppy` (WL_F64 or
+ * WL_F32) reduces it by the factor `delta` in (0, 1) (straight to the
+ * tolerance when sloppy is WL_F64), and the correction is added to the FP64 x.
+ * Stops when |eta - D_ov x| <= tol |eta| with the FP64 operator.  mass must be
+ * > 0 (D_ov(0) has exact zero modes).  maxiter bounds the inner iterations in
+ * total.  info: host array of nrhs entries; iters = inner iterations,
+ * reliable_updates = recomputed residuals after the first, true_resid = the
+ * final FP64 relative residual.  A zero source gives x = 0.  Returns
+ * WL_ERR_NOCONV with x = the best iterate when tol is not reached.
+ * Synchronises `stream`. */
+wl_status overlap_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double rho, double mass,
+                     int32_t degree, double lo, double hi, double scale, double tol, int32_t maxiter,
+                     wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info, void *stream);
+
 /* Largest eigenvalue of H_W^2 (m0 = -rho) estimated by `iters` steps of power
  * iteration from the canonical field v0 (device); FP64.  Synchronises. */
 wl_status wl_hw2_lmax(wl_gauge U, double rho, const double *v0, int32_t iters, double *lmax, void *stream);
@@ -188,10 +221,15 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
  * bandwidth reference for the roofline; mean seconds per copy. */
 wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, void *stream);
 
-/* Per-kernel timing of the library's own launches: when enabled, every hop
- * launch is bracketed by HIP events on its stream and its duration added to a
- * running total.  wl_prof_read returns launches and total milliseconds of hop
- * launches since the last reset and resets the counters. */
+/* Per-kernel timing of the library's own hop launches.  on = 1: every hop
+ * launch is timed -- eager launches are dispatched with start/end HIP events
+ * that the dispatch records at the kernel's start and end, and hops captured
+ * into a solver's graph get event-record nodes around them, read after every
+ * replay (such timed graphs are captured separately from untimed ones).
+ * on = 2: only the graph-replayed hops are timed (eager intervals include the
+ * dispatch latency).  on = 0: off.  wl_prof_read returns launches, total
+ * milliseconds and algorithmic GB of the timed launches since the last read
+ * and resets the counters. */
 wl_status wl_prof_enable(int32_t on);
 wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes);
 

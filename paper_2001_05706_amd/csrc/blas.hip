@@ -259,6 +259,20 @@ __global__ __launch_bounds__(256) void k_cdot(BlasArgs a)
     block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
 }
 
+// y = g5 x: spins 2 and 3 (the last 12 reals of a site) change sign
+template <int P>
+__global__ __launch_bounds__(256) void k_g5copy(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    T x[24];
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
+#pragma unroll
+    for (int k = 12; k < 24; ++k) x[k] = -x[k];
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+}
+
 template <int PD, int PS>
 __global__ __launch_bounds__(256) void k_convert(BlasArgs a)
 {
@@ -291,6 +305,7 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
     case BL_BICG_S: hipLaunchKernelGGL(k_bicg_s<P>, g, b, 0, s, a); break;
     case BL_BICG_XR: hipLaunchKernelGGL(k_bicg_xr<P>, g, b, 0, s, a); break;
     case BL_CDOT: hipLaunchKernelGGL(k_cdot<P>, g, b, 0, s, a); break;
+    case BL_G5COPY: hipLaunchKernelGGL(k_g5copy<P>, g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

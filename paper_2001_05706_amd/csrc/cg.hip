@@ -224,12 +224,14 @@ struct Cg {
 
     wl_status chunk(int k)
     {
-        if (!use_graphs || prof().on) {
+        if (!use_graphs) {
             for (int j = 0; j < k; ++j) WL_TRY(iteration(S.hist + (size_t)j * S.nvec));
             return WL_OK;
         }
+        // a timed graph carries event-record nodes around its hops: it is a graph of its own
+        Prof &P = prof();
         const std::string key = "cg/" + std::to_string(method) + "/" + std::to_string(k) + "/" +
-                                std::to_string(sloppy) + "/" + std::to_string(recon);
+                                std::to_string(sloppy) + "/" + std::to_string(recon) + (P.on ? "/timed" : "");
         auto it = S.graphs.find(key);
         if (it == S.graphs.end()) {
             const SysDesc *tab = nullptr;  // packed links and tables exist before capture
@@ -239,11 +241,14 @@ struct Cg {
             const double saved = g_bytes_acc;
             hipStream_t user = s;
             s = cs;
+            EventList evl;
+            if (P.on) P.capture = &evl;
             WL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
             wl_status st = WL_OK;
             for (int j = 0; j < k && st == WL_OK; ++j) st = iteration(S.hist + (size_t)j * S.nvec);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(cs, &g);
+            P.capture = nullptr;
             s = user;
             g_bytes_acc = saved;
             if (st != WL_OK) {
@@ -256,9 +261,14 @@ struct Cg {
             (void)hipGraphDestroy(g);
             if (ie != hipSuccess) return set_error(WL_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
             it = S.graphs.emplace(key, ex).first;
+            if (P.on) P.graph[(const void *)ex] = std::move(evl);
         }
         g_bytes_acc += k * iteration_bytes();
         WL_HIP(hipGraphLaunch(it->second, s));
+        if (P.on) {
+            auto ev = P.graph.find((const void *)it->second);
+            P.replayed = ev == P.graph.end() ? nullptr : &ev->second;
+        }
         return WL_OK;
     }
 };
@@ -405,6 +415,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
             int32_t *hbad = (int32_t *)(hp + (size_t)ExecSet::kHist * nv);
             WL_HIP(hipMemcpyAsync(hbad, S.bad, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, s));
             WL_HIP(hipStreamSynchronize(s));
+            prof_collect_graph();  // a replayed graph's events are read before its next replay
             if (trace) {
                 double sc[ExecSet::SC_N];
                 for (int j = 0; j < ExecSet::SC_N; ++j)

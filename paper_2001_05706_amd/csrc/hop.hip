@@ -8,6 +8,8 @@
 // site.  Links are read with non-temporal loads (each is used once per hop);
 // neighbour spinors are shared by up to 8 output sites through L2, which the
 // XCD-aware block order keeps on one die.
+#include <hip/hip_ext.h>
+
 #include "wl_reduce.h"
 #include "wl_kernels.h"
 
@@ -19,7 +21,7 @@ namespace wl {
 //   nt:    non-temporal link loads (links used once) or cached (shared by RHS)
 template <int SP, int VAR> struct HopVar {
     static constexpr int fence = VAR == 0 || VAR == 3 ? 2 : 1;
-    static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR == 3 ? 3 : 4) : (VAR == 0 || VAR == 3 ? 4 : VAR == 1 ? 5 : 6);
+    static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR == 3 ? 2 : 3) : (VAR == 0 || VAR == 3 ? 4 : VAR == 1 ? 5 : 6);
     static constexpr bool nt = VAR != 3;
 };
 constexpr int kHopVariants = 4;
@@ -98,38 +100,52 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
 }
 
+// With events, the dispatch itself records them at the kernel's start and end
+// (the kernel-timing form of the launch), so the measured interval is the
+// kernel alone.
+template <class K>
+static void dispatch(K kernel, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, dim3(a.nblocks), dim3(block), 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, dim3(a.nblocks), dim3(block), 0, s, a);
+}
+
 template <int SP, int GP, int R, int VAR>
-static hipError_t launch_hop_v(bool dag, const HopArgs &a, int block, hipStream_t s)
+static hipError_t launch_hop_v(bool dag, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (dag)
-        hipLaunchKernelGGL((k_hop<SP, GP, R, true, VAR>), dim3(a.nblocks), dim3(block), 0, s, a);
+        dispatch(k_hop<SP, GP, R, true, VAR>, a, block, s, e0, e1);
     else
-        hipLaunchKernelGGL((k_hop<SP, GP, R, false, VAR>), dim3(a.nblocks), dim3(block), 0, s, a);
+        dispatch(k_hop<SP, GP, R, false, VAR>, a, block, s, e0, e1);
     return hipGetLastError();
 }
 
 template <int SP, int GP, int R>
-static hipError_t launch_hop_t(int var, bool dag, const HopArgs &a, int block, hipStream_t s)
+static hipError_t launch_hop_t(int var, bool dag, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1)
 {
     switch (var) {
-    case 0: return launch_hop_v<SP, GP, R, 0>(dag, a, block, s);
-    case 1: return launch_hop_v<SP, GP, R, 1>(dag, a, block, s);
-    case 2: return launch_hop_v<SP, GP, R, 2>(dag, a, block, s);
-    case 3: return launch_hop_v<SP, GP, R, 3>(dag, a, block, s);
+    case 0: return launch_hop_v<SP, GP, R, 0>(dag, a, block, s, e0, e1);
+    case 1: return launch_hop_v<SP, GP, R, 1>(dag, a, block, s, e0, e1);
+    case 2: return launch_hop_v<SP, GP, R, 2>(dag, a, block, s, e0, e1);
+    case 3: return launch_hop_v<SP, GP, R, 3>(dag, a, block, s, e0, e1);
     }
     return hipErrorInvalidValue;
 }
 
 int hop_variants() { return kHopVariants; }
 
-hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s)
+hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1)
 {
-    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(var, dag, a, block, s);
-    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(var, dag, a, block, s);
-    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(var, dag, a, block, s);
-    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(var, dag, a, block, s);
-    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(var, dag, a, block, s);
-    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(var, dag, a, block, s);
+    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(var, dag, a, block, s, e0, e1);
+    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(var, dag, a, block, s, e0, e1);
+    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(var, dag, a, block, s, e0, e1);
+    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(var, dag, a, block, s, e0, e1);
+    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(var, dag, a, block, s, e0, e1);
+    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(var, dag, a, block, s, e0, e1);
     return hipErrorInvalidValue;
 }
 

@@ -100,19 +100,38 @@ Prof &prof()
 void prof_collect()
 {
     Prof &p = prof();
-    for (size_t i = 0; i < p.pending.size(); ++i) {
+    for (size_t i = 0; i < p.pending.ev.size(); ++i) {
         float ms = 0.f;
-        if (hipEventSynchronize(p.pending[i].second) == hipSuccess &&
-            hipEventElapsedTime(&ms, p.pending[i].first, p.pending[i].second) == hipSuccess) {
+        if (hipEventSynchronize(p.pending.ev[i].second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.pending.ev[i].first, p.pending.ev[i].second) == hipSuccess) {
             p.ms += ms;
             p.launches += 1;
-            p.gbytes += p.pending_bytes[i];
+            p.gbytes += p.pending.gbytes[i];
         }
-        (void)hipEventDestroy(p.pending[i].first);
-        (void)hipEventDestroy(p.pending[i].second);
+        (void)hipEventDestroy(p.pending.ev[i].first);
+        (void)hipEventDestroy(p.pending.ev[i].second);
     }
-    p.pending.clear();
-    p.pending_bytes.clear();
+    p.pending.ev.clear();
+    p.pending.gbytes.clear();
+    prof_collect_graph();
+}
+
+void prof_collect_graph()
+{
+    Prof &p = prof();
+    if (!p.replayed) return;
+    const EventList &L = *p.replayed;
+    for (size_t i = 0; i < L.ev.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, L.ev[i].first, L.ev[i].second) == hipSuccess) {
+            p.ms += ms;
+            p.launches += 1;
+            p.gbytes += L.gbytes[i];
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    p.replayed = nullptr;
 }
 
 bool capturing(hipStream_t s)
@@ -222,7 +241,19 @@ ExecSet::ExecSet(const std::vector<SysEntry> &s) : systems(s) {}
 
 ExecSet::~ExecSet()
 {
-    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    Prof &P = prof();
+    for (auto &kv : graphs) {
+        auto ev = P.graph.find((const void *)kv.second);
+        if (ev != P.graph.end()) {
+            if (P.replayed == &ev->second) P.replayed = nullptr;
+            for (auto &e : ev->second.ev) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
+            P.graph.erase(ev);
+        }
+        (void)hipGraphExecDestroy(kv.second);
+    }
     for (auto &kv : fields) {
         (void)hipFree(kv.second.p);
         (void)hipFree(kv.second.n);
@@ -545,20 +576,30 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
     const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active);
     g_bytes_acc += bytes;
     Prof &P = prof();
-    const bool timed = P.on && (P.prec < 0 || P.prec == prec) && !capturing(s);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
+    const bool want = P.on && (P.prec < 0 || P.prec == prec);
+    const bool cap = capturing(s);
+    if (want && cap && P.capture) {
+        // event-record nodes around the hop node of the graph being captured
+        hipEvent_t e0 = nullptr, e1 = nullptr;
         WL_HIP(hipEventCreate(&e0));
         WL_HIP(hipEventCreate(&e1));
         WL_HIP(hipEventRecord(e0, s));
-    }
-    WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
-    if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, use_active ? S.d_active : nullptr, S.nvec, s));
-    if (timed) {
+        WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
         WL_HIP(hipEventRecord(e1, s));
-        P.pending.push_back({e0, e1});
-        P.pending_bytes.push_back(bytes * 1e-9);
+        P.capture->ev.push_back({e0, e1});
+        P.capture->gbytes.push_back(bytes * 1e-9);
+    } else if (want && !cap && !P.graphs_only) {
+        // the dispatch records the events at the kernel's start and end
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        WL_HIP(hipEventCreate(&e0));
+        WL_HIP(hipEventCreate(&e1));
+        WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s, e0, e1));
+        P.pending.ev.push_back({e0, e1});
+        P.pending.gbytes.push_back(bytes * 1e-9);
+    } else {
+        WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
     }
+    if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, use_active ? S.d_active : nullptr, S.nvec, s));
     return WL_OK;
 }
 
@@ -585,7 +626,7 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.sc = S.sc;
     a.nvec = S.nvec;
     a.red = red;
-    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2};
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2};
     if (op == BL_ACCUM)
         g_bytes_acc += blas_bytes(S, P_F64, 2, use_active) + blas_bytes(S, prec, 2, use_active);
     else
@@ -805,8 +846,10 @@ double wl_hop_bytes_per_site(wl_prec prec, int32_t recon, int32_t nrhs)
 wl_status wl_prof_enable(int32_t on)
 {
     clear_error();
+    if (on < 0 || on > 2) return set_error(WL_ERR_ARG, "on must be 0, 1 or 2");
     Prof &P = prof();
     P.on = on != 0;
+    P.graphs_only = on == 2;
     return WL_OK;
 }
 

@@ -36,7 +36,7 @@ static std::vector<double> invsqrt_coeffs(int degree, double lo, double hi)
 }
 
 // H_W applied to the two parities of `in` into `out`; coef = {m a, ..., c} per system
-static wl_status apply_hw(ExecSet &S, int prec, int recon, const Field out[2], const Field in[2], const double *coef,
+wl_status apply_hw(ExecSet &S, int prec, int recon, const Field out[2], const Field in[2], const double *coef,
                           const RedSpec *red, hipStream_t s)
 {
     for (int p = 0; p < 2; ++p) {
@@ -51,7 +51,7 @@ static wl_status apply_hw(ExecSet &S, int prec, int recon, const Field out[2], c
 }
 
 // power iteration for lambda_max(H_W^2) on vector 0 of the set; FP64
-static wl_status power_lmax(ExecSet &S, double rho, int recon, int iters, const Field u[2], double *lmax,
+wl_status power_lmax(ExecSet &S, double rho, int recon, int iters, const Field u[2], double *lmax,
                             hipStream_t s)
 {
     Field w[2];
@@ -79,6 +79,87 @@ static wl_status power_lmax(ExecSet &S, double rho, int recon, int iters, const 
     WL_HIP(hipStreamSynchronize(s));
     if (!std::isfinite(h)) return set_error(WL_ERR_NONFINITE, "non-finite power iteration");
     *lmax = h;
+    return WL_OK;
+}
+
+// 1.02 x the power-iteration estimate (100 steps) of lambda_max(H_W^2), started
+// from the first canonical field of v0
+wl_status hw2_scale(wl_gauge U, double rho, const double *v0, hipStream_t s, double *scale)
+{
+    ExecSet *S1 = nullptr;
+    WL_TRY(get_set({SysEntry{U, 1, 1.0 / (8.0 - 2.0 * rho)}}, &S1));
+    std::fill(S1->h_active.begin(), S1->h_active.end(), 1);
+    WL_TRY(S1->upload_active(s));
+    Field u[2];
+    WL_TRY(S1->field("pw_u0", P_F64, &u[0]));
+    WL_TRY(S1->field("pw_u1", P_F64, &u[1]));
+    const double *c[1] = {v0};
+    WL_TRY(pack(*S1, c, 0, u[0], s));
+    WL_TRY(pack(*S1, c, 1, u[1], s));
+    double lm = 0;
+    WL_TRY(power_lmax(*S1, rho, 18, 100, u, &lm, s));
+    *scale = 1.02 * lm;
+    if (!(*scale > 0)) return set_error(WL_ERR_NONFINITE, "power iteration gave %g", lm);
+    return WL_OK;
+}
+
+wl_status sign_plan(ExecSet &S, double rho, int degree, double lo, double hi, double scale, SignPlan *P)
+{
+    const int N = degree + 1;
+    const std::vector<double> c = invsqrt_coeffs(degree, lo, hi);
+    const double m = 4.0 - rho;
+    const double ay = 2.0 / ((hi - lo) * scale), by = -(hi + lo) / (hi - lo);
+    // coefficient rows: [0] H_W, [1..N-1] Clenshaw steps j, [N] final p v
+    std::vector<double> tab;
+    tab.insert(tab.end(), {m, 0, 0, 0, -0.5});
+    for (int j = 1; j < N; ++j) tab.insert(tab.end(), {2 * ay * m, 2 * by, -1.0, c[j], -ay});
+    tab.insert(tab.end(), {ay * m, by, -1.0, 0.5 * c[0], -0.5 * ay});
+    P->N = N;
+    P->m = m;
+    P->rs = 1.0 / std::sqrt(scale);
+    return coef_table(S, tab, &P->tab);
+}
+
+wl_status sign_poly(ExecSet &S, int prec, int recon, const SignPlan &P, const Field v[2], Field y[2], hipStream_t s)
+{
+    Field b[3][2], w[2];
+    for (int p = 0; p < 2; ++p) {
+        WL_TRY(S.field("sg_w" + std::to_string(p), prec, &w[p]));
+        for (int j = 0; j < 3; ++j) WL_TRY(S.field("sg_b" + std::to_string(j) + std::to_string(p), prec, &b[j][p]));
+    }
+    // b_{N} = b_{N+1} = 0
+    int i0 = 0, i1 = 1, i2 = 2;  // b_j, b_{j+1}, b_{j+2}
+    for (int p = 0; p < 2; ++p) {
+        WL_TRY(blas(S, BL_ZERO, prec, &b[i1][p], 1, nullptr, no_red(), s));
+        WL_TRY(blas(S, BL_ZERO, prec, &b[i2][p], 1, nullptr, no_red(), s));
+    }
+    auto step = [&](const double *coef, const Field *dst) -> wl_status {
+        // w = H_W b_{j+1};  dst = g5(a0 w + c hop w) + a1 b_{j+1} + a2 b_{j+2} + a3 v
+        WL_TRY(apply_hw(S, prec, recon, w, b[i1], P.tab, nullptr, s));
+        for (int p = 0; p < 2; ++p) {
+            Epi e;
+            e.coef = coef;
+            e.g5 = 1;
+            e.nx = 4;
+            e.X[0] = w[p];
+            e.X[1] = b[i1][p];
+            e.X[2] = b[i2][p];
+            e.X[3] = v[p];
+            WL_TRY(hop(S, prec, recon, false, p, dst[p], w[1 - p], e, no_red(), s));
+        }
+        return WL_OK;
+    };
+    for (int j = P.N - 1; j >= 1; --j) {
+        WL_TRY(step(P.tab + 5 * j, b[i0]));
+        const int t = i2;
+        i2 = i1;
+        i1 = i0;
+        i0 = t;
+    }
+    // p v = Y b_1 - b_2 + c_0 v / 2
+    WL_TRY(step(P.tab + 5 * P.N, b[i0]));
+    y[0] = b[i0][0];
+    y[1] = b[i0][1];
     return WL_OK;
 }
 
@@ -136,76 +217,21 @@ wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t n
     const double *cin[1] = {in};
     double *cout[1] = {out};
 
-    if (!(scale > 0)) {
-        // 1.02 x the power-iteration estimate of lambda_max(H_W^2), from input vector 0
-        ExecSet *S1 = nullptr;
-        WL_TRY(get_set({SysEntry{U, 1, 1.0 / (8.0 - 2.0 * rho)}}, &S1));
-        std::fill(S1->h_active.begin(), S1->h_active.end(), 1);
-        WL_TRY(S1->upload_active(s));
-        Field u[2];
-        WL_TRY(S1->field("pw_u0", P_F64, &u[0]));
-        WL_TRY(S1->field("pw_u1", P_F64, &u[1]));
-        WL_TRY(pack(*S1, cin, 0, u[0], s));
-        WL_TRY(pack(*S1, cin, 1, u[1], s));
-        double lm = 0;
-        WL_TRY(power_lmax(*S1, rho, 18, 100, u, &lm, s));
-        scale = 1.02 * lm;
-        if (!(scale > 0)) return set_error(WL_ERR_NONFINITE, "power iteration gave %g", lm);
-    }
+    if (!(scale > 0)) WL_TRY(hw2_scale(U, rho, in, s, &scale));
 
-    Field v[2], b[3][2], w[2];
+    Field v[2], w[2], y[2];
     for (int p = 0; p < 2; ++p) {
         WL_TRY(S->field("sg_v" + std::to_string(p), prec, &v[p]));
         WL_TRY(S->field("sg_w" + std::to_string(p), prec, &w[p]));
-        for (int j = 0; j < 3; ++j) WL_TRY(S->field("sg_b" + std::to_string(j) + std::to_string(p), prec, &b[j][p]));
         WL_TRY(pack(*S, cin, p, v[p], s));
     }
-    const int N = degree + 1;
-    const std::vector<double> c = invsqrt_coeffs(degree, lo, hi);
-    const double m = 4.0 - rho;
-    const double ay = 2.0 / ((hi - lo) * scale), by = -(hi + lo) / (hi - lo);
-    const double rs = 1.0 / std::sqrt(scale);
-    // coefficient rows: [0] H_W, [1..N-1] Clenshaw steps j, [N] final p v, [N+1] output
-    std::vector<double> tab;
-    tab.insert(tab.end(), {m, 0, 0, 0, -0.5});
-    for (int j = 1; j < N; ++j) tab.insert(tab.end(), {2 * ay * m, 2 * by, -1.0, c[j], -ay});
-    tab.insert(tab.end(), {ay * m, by, -1.0, 0.5 * c[0], -0.5 * ay});
-    tab.insert(tab.end(), {rs * m, 0, 0, 0, -0.5 * rs});
-    const double *dtab = nullptr;
-    WL_TRY(coef_table(*S, tab, &dtab));
-
-    // b_{N} = b_{N+1} = 0
-    int i0 = 0, i1 = 1, i2 = 2;  // b_j, b_{j+1}, b_{j+2}
-    for (int p = 0; p < 2; ++p) {
-        WL_TRY(blas(*S, BL_ZERO, prec, &b[i1][p], 1, nullptr, no_red(), s));
-        WL_TRY(blas(*S, BL_ZERO, prec, &b[i2][p], 1, nullptr, no_red(), s));
-    }
-    auto step = [&](const double *coef, const Field *dst) -> wl_status {
-        // w = H_W b_{j+1};  dst = g5(a0 w + c hop w) + a1 b_{j+1} + a2 b_{j+2} + a3 v
-        WL_TRY(apply_hw(*S, prec, recon, w, b[i1], dtab, nullptr, s));
-        for (int p = 0; p < 2; ++p) {
-            Epi e;
-            e.coef = coef;
-            e.g5 = 1;
-            e.nx = 4;
-            e.X[0] = w[p];
-            e.X[1] = b[i1][p];
-            e.X[2] = b[i2][p];
-            e.X[3] = v[p];
-            WL_TRY(hop(*S, prec, recon, false, p, dst[p], w[1 - p], e, no_red(), s));
-        }
-        return WL_OK;
-    };
-    for (int j = N - 1; j >= 1; --j) {
-        WL_TRY(step(dtab + 5 * j, b[i0]));
-        const int t = i2;
-        i2 = i1;
-        i1 = i0;
-        i0 = t;
-    }
-    // p v = Y b_1 - b_2 + c_0 v / 2 into b[i0]; then out = s^{-1/2} H_W (p v)
-    WL_TRY(step(dtab + 5 * N, b[i0]));
-    WL_TRY(apply_hw(*S, prec, recon, w, b[i0], dtab + 5 * (N + 1), nullptr, s));
+    SignPlan P;
+    WL_TRY(sign_plan(*S, rho, degree, lo, hi, scale, &P));
+    WL_TRY(sign_poly(*S, prec, recon, P, v, y, s));
+    // out = s^{-1/2} H_W (p v)
+    const double *orow = nullptr;
+    WL_TRY(coef_table(*S, {P.rs * P.m, 0, 0, 0, -0.5 * P.rs}, &orow));
+    WL_TRY(apply_hw(*S, prec, recon, w, y, orow, nullptr, s));
     for (int p = 0; p < 2; ++p) WL_TRY(unpack(*S, cout, p, w[p], s));
     WL_HIP(hipStreamSynchronize(s));
     return WL_OK;

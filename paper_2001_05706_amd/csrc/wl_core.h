@@ -49,6 +49,10 @@ template <class T> WL_HD cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, 
 template <class T> WL_HD cpx<T> cadd_i(cpx<T> a, cpx<T> b) { return {a.re - b.im, a.im + b.re}; }
 template <class T> WL_HD cpx<T> csub_i(cpx<T> a, cpx<T> b) { return {a.re + b.im, a.im - b.re}; }
 
+// fused multiply-add, one rounding (IEEE fma on host and device)
+WL_HD float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
+WL_HD double fmadd(double a, double b, double c) { return fma(a, b, c); }
+
 // ------------------------------------------------------------------ half / bf16
 
 WL_HD float bf16_to_float(uint16_t h)
@@ -319,13 +323,28 @@ WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
         }
     }
     if constexpr (R == 12) {
-        // row2 = conj(row0 x row1)
-        u[2][0] = {u[0][1].re * u[1][2].re - u[0][1].im * u[1][2].im - (u[0][2].re * u[1][1].re - u[0][2].im * u[1][1].im),
-                   -(u[0][1].re * u[1][2].im + u[0][1].im * u[1][2].re - (u[0][2].re * u[1][1].im + u[0][2].im * u[1][1].re))};
-        u[2][1] = {u[0][2].re * u[1][0].re - u[0][2].im * u[1][0].im - (u[0][0].re * u[1][2].re - u[0][0].im * u[1][2].im),
-                   -(u[0][2].re * u[1][0].im + u[0][2].im * u[1][0].re - (u[0][0].re * u[1][2].im + u[0][0].im * u[1][2].re))};
-        u[2][2] = {u[0][0].re * u[1][1].re - u[0][0].im * u[1][1].im - (u[0][1].re * u[1][0].re - u[0][1].im * u[1][0].im),
-                   -(u[0][0].re * u[1][1].im + u[0][0].im * u[1][1].re - (u[0][1].re * u[1][0].im + u[0][1].im * u[1][0].re))};
+        // row2 = conj(row0 x row1): u2k = conj(u0i u1j - u0j u1i), (k, i, j) cyclic
+        auto cross = [](cpx<T> a, cpx<T> b, cpx<T> c, cpx<T> d) -> cpx<T> {
+            if constexpr (sizeof(T) == 4) {
+                // FP32 arithmetic: chains of fused multiply-adds (fewer instructions)
+                T re = a.re * b.re;
+                re = fmadd(-a.im, b.im, re);
+                re = fmadd(-c.re, d.re, re);
+                re = fmadd(c.im, d.im, re);
+                T im = c.re * d.im;
+                im = fmadd(c.im, d.re, im);
+                im = fmadd(-a.re, b.im, im);
+                im = fmadd(-a.im, b.re, im);
+                return {re, im};
+            } else {
+                // FP64 (memory-bound): independent products keep fewer registers live
+                return {a.re * b.re - a.im * b.im - (c.re * d.re - c.im * d.im),
+                        -(a.re * b.im + a.im * b.re - (c.re * d.im + c.im * d.re))};
+            }
+        };
+        u[2][0] = cross(u[0][1], u[1][2], u[0][2], u[1][1]);
+        u[2][1] = cross(u[0][2], u[1][0], u[0][0], u[1][2]);
+        u[2][2] = cross(u[0][0], u[1][1], u[0][1], u[1][0]);
     }
 }
 
@@ -415,6 +434,45 @@ WL_HD void project(const T v[24], cpx<T> h0[3], cpx<T> h1[3])
     }
 }
 
+// f (a + s b) for s = +1, -1, +i, -i (S = 0, 1, 2, 3): one multiply and one
+// fused multiply-add per real output, so that half-precision inputs can enter
+// the mixed-precision fma directly
+template <int S, class T> WL_HD cpx<T> comb_scaled(cpx<T> a, cpx<T> b, T f, T nf)
+{
+    if constexpr (S == 0) return {fmadd(a.re, f, b.re * f), fmadd(a.im, f, b.im * f)};
+    if constexpr (S == 1) return {fmadd(a.re, f, b.re * nf), fmadd(a.im, f, b.im * nf)};
+    if constexpr (S == 2) return {fmadd(a.re, f, b.im * nf), fmadd(a.im, f, b.re * f)};
+    return {fmadd(a.re, f, b.im * f), fmadd(a.im, f, b.re * nf)};
+}
+
+// f P psi (the projection of `project`, scaled by f)
+template <int MU, int SG, class T>
+WL_HD void project_scaled(const T v[24], T f, cpx<T> h0[3], cpx<T> h1[3])
+{
+    const T nf = -f;
+    constexpr int ADD = 0, SUB = 1, ADD_I = 2, SUB_I = 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cpx<T> p0{v[2 * (0 + c)], v[2 * (0 + c) + 1]};
+        cpx<T> p1{v[2 * (3 + c)], v[2 * (3 + c) + 1]};
+        cpx<T> p2{v[2 * (6 + c)], v[2 * (6 + c) + 1]};
+        cpx<T> p3{v[2 * (9 + c)], v[2 * (9 + c) + 1]};
+        if constexpr (MU == 0) {
+            h0[c] = comb_scaled<(SG > 0 ? ADD_I : SUB_I)>(p0, p3, f, nf);
+            h1[c] = comb_scaled<(SG > 0 ? ADD_I : SUB_I)>(p1, p2, f, nf);
+        } else if constexpr (MU == 1) {
+            h0[c] = comb_scaled<(SG > 0 ? SUB : ADD)>(p0, p3, f, nf);
+            h1[c] = comb_scaled<(SG > 0 ? ADD : SUB)>(p1, p2, f, nf);
+        } else if constexpr (MU == 2) {
+            h0[c] = comb_scaled<(SG > 0 ? ADD_I : SUB_I)>(p0, p2, f, nf);
+            h1[c] = comb_scaled<(SG > 0 ? SUB_I : ADD_I)>(p1, p3, f, nf);
+        } else {
+            h0[c] = comb_scaled<(SG > 0 ? ADD : SUB)>(p0, p2, f, nf);
+            h1[c] = comb_scaled<(SG > 0 ? ADD : SUB)>(p1, p3, f, nf);
+        }
+    }
+}
+
 // acc += P psi given U h0, U h1 (already multiplied by the link)
 template <int MU, int SG, class T>
 WL_HD void reconstruct_add(T acc[24], const cpx<T> g0[3], const cpx<T> g1[3])
@@ -447,26 +505,45 @@ WL_HD void reconstruct_add(T acc[24], const cpx<T> g0[3], const cpx<T> g1[3])
     }
 }
 
-// g = U h (ADJ = false) or U^dagger h (ADJ = true)
+// g = U h (ADJ = false) or U^dagger h (ADJ = true); in FP32 each output is a
+// chain of fused multiply-adds
 template <bool ADJ, class T>
 WL_HD void su3_mul(const cpx<T> u[3][3], const cpx<T> h[3], cpx<T> g[3])
 {
+    if constexpr (sizeof(T) == 8) {
+        // FP64 (memory-bound): independent products keep fewer registers live
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        cpx<T> s{0, 0};
+        for (int a = 0; a < 3; ++a) {
+            cpx<T> s{0, 0};
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            if constexpr (ADJ) {
-                cpx<T> p = cjmul(u[b][a], h[b]);
-                s.re += p.re;
-                s.im += p.im;
-            } else {
-                cpx<T> p = cmul(u[a][b], h[b]);
+            for (int b = 0; b < 3; ++b) {
+                const cpx<T> p = ADJ ? cjmul(u[b][a], h[b]) : cmul(u[a][b], h[b]);
                 s.re += p.re;
                 s.im += p.im;
             }
+            g[a] = s;
         }
-        g[a] = s;
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T re = 0, im = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const cpx<T> w = ADJ ? u[b][a] : u[a][b];
+            // U h: (w.re h.re - w.im h.im, w.re h.im + w.im h.re); U^dagger: conj(w)
+            const T wi = ADJ ? -w.im : w.im;
+            if (b == 0) {
+                re = w.re * h[b].re;
+                im = w.re * h[b].im;
+            } else {
+                re = fmadd(w.re, h[b].re, re);
+                im = fmadd(w.re, h[b].im, im);
+            }
+            re = fmadd(-wi, h[b].im, re);
+            im = fmadd(wi, h[b].re, im);
+        }
+        g[a] = {re, im};
     }
 }
 
@@ -504,20 +581,20 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
     // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
     constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
     cpx<T> h0[3], h1[3];
-    project<MU, SG>(v, h0, h1);
     if constexpr (SP == P_F16 || SP == P_BF16) {
-        // site norm of the half-precision neighbour and the boundary sign, on 12 values
-        const T f = flip ? -nrm : nrm;
+        // site norm of the half-precision neighbour and the boundary sign,
+        // folded into the projection
+        project_scaled<MU, SG>(v, flip ? -nrm : nrm, h0, h1);
+    } else {
+        project<MU, SG>(v, h0, h1);
+    }
+    if constexpr (SP == P_F64 || SP == P_F32) {
+        if (flip) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            h0[c] = {f * h0[c].re, f * h0[c].im};
-            h1[c] = {f * h1[c].re, f * h1[c].im};
-        }
-    } else if (flip) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            h0[c] = {-h0[c].re, -h0[c].im};
-            h1[c] = {-h1[c].re, -h1[c].im};
+            for (int c = 0; c < 3; ++c) {
+                h0[c] = {-h0[c].re, -h0[c].im};
+                h1[c] = {-h1[c].re, -h1[c].im};
+            }
         }
     }
     // forward: U_mu(x) on this parity; backward: U_mu(x - mu)^dagger on the other parity

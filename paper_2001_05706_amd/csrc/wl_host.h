@@ -156,6 +156,26 @@ wl_status zero_canon(ExecSet &S, double *const *canon, int parity, hipStream_t s
 // device coefficient tables [nsys][5], cached by content
 wl_status coef_table(ExecSet &S, const std::vector<double> &c, const double **out);
 
+// ------------------------------------------------------------------ sign function (sign.hip)
+
+// Chebyshev plan of eps(H_W) ~= s^{-1/2} H_W p(H_W^2 / s) for a single-system
+// set: device coefficient rows [0] H_W, [1 .. N-1] Clenshaw steps, [N] final p v.
+struct SignPlan {
+    int N = 0;       // degree + 1
+    double m = 0;    // 4 - rho
+    double rs = 0;   // s^{-1/2}
+    const double *tab = nullptr;
+};
+wl_status sign_plan(ExecSet &S, double rho, int degree, double lo, double hi, double scale, SignPlan *P);
+// y = p(H_W^2 / s) v on both parities of every active vector; y aliases scratch
+// fields of the set that the next sign_poly call in the same precision reuses
+wl_status sign_poly(ExecSet &S, int prec, int recon, const SignPlan &P, const Field v[2], Field y[2], hipStream_t s);
+// out_p = G5(a0 in_p + c hop(in)_p) on both parities with the coefficient row coef
+wl_status apply_hw(ExecSet &S, int prec, int recon, const Field out[2], const Field in[2], const double *coef,
+                   const RedSpec *red, hipStream_t s);
+wl_status power_lmax(ExecSet &S, double rho, int recon, int iters, const Field u[2], double *lmax, hipStream_t s);
+wl_status hw2_scale(wl_gauge U, double rho, const double *v0, hipStream_t s, double *scale);
+
 // ------------------------------------------------------------------ tuning and timing
 
 int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream_t s,
@@ -164,17 +184,32 @@ bool capturing(hipStream_t s);
 std::string hop_key(const ExecSet &S, int prec, int recon, bool dag);
 std::vector<int> hop_candidates();
 
+// Event pairs around hop launches and the algorithmic GB of each launch
+struct EventList {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<double> gbytes;
+};
+
+// Kernel timing of hop launches.  Eager launches carry start/end events of
+// their own dispatch; launches captured into a graph get event-record nodes
+// around them, read after every replay of that graph (the CP has the next
+// packet in hand, so graph intervals carry almost no launch latency).
 struct Prof {
     bool on = false;
-    int prec = -1;  // storage precision of the hops timed (-1: all)
+    bool graphs_only = false;  // time only launches replayed from graphs
+    int prec = -1;             // storage precision of the hops timed (-1: all)
     int64_t launches = 0;
     double ms = 0.0;
     double gbytes = 0.0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-    std::vector<double> pending_bytes;
+    EventList pending;                        // eager launches, read once
+    EventList *capture = nullptr;             // graph being captured: its hop events
+    std::map<const void *, EventList> graph;  // per instantiated graph
+    const EventList *replayed = nullptr;      // events of the last replayed graph
 };
 Prof &prof();
 void prof_collect();
+// accumulate the events of the last replayed graph (its stream must be synchronised)
+void prof_collect_graph();
 
 // algorithmic bytes of one hop on all active vectors of the set
 double hop_bytes(const ExecSet &S, int prec, int recon, bool use_active);

@@ -35,8 +35,10 @@ struct PackArgs {
 };
 
 // hop.hip
-// var selects a launch variant (0 .. hop_variants()-1, see hop.hip)
-hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s);
+// var selects a launch variant (0 .. hop_variants()-1, see hop.hip); with
+// events e0/e1 the dispatch records them at the kernel's start and end
+hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 int hop_variants();
 
 // blas.hip -- all operate on the vectors of one set through its block map
@@ -54,6 +56,7 @@ enum BlasOp {
     BL_BICG_S = 9,     // s = r - alpha v                                                   f = {s, r, v}
     BL_BICG_XR = 10,   // x += alpha p + omega s; r = s - omega t; <rhat, r>, |r|^2         f = {x, p, s, r, t, rhat}
     BL_CDOT = 11,      // <a, b>                                                            f = {a, b}
+    BL_G5COPY = 12,    // y = g5 x                                                          f = {y, x}
 };
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
 // fixed-order sum of each active vector's block partials and the reduction's finishing step

@@ -63,6 +63,9 @@ SIGNATURES = [
                                ctypes.POINTER(_i32), ctypes.POINTER(_d), _d, _i32, _i32, _i32, _d,
                                ctypes.POINTER(WlSolveInfo), _P]),
     ("overlap_sign_cheb", _i32, [_P, _P, _P, _i32, _d, _i32, _d, _d, _d, _i32, _i32, _P]),
+    ("overlap_dslash", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _i32, _i32, _i32, _P]),
+    ("overlap_cg", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _d, _i32, _i32, _i32, _d,
+                          ctypes.POINTER(WlSolveInfo), _P]),
     ("wl_hw2_lmax", _i32, [_P, _d, _P, _i32, ctypes.POINTER(_d), _P]),
     ("wl_status_string", ctypes.c_char_p, [_i32]),
     ("wl_last_error", ctypes.c_char_p, []),
@@ -214,6 +217,25 @@ def overlap_sign_cheb(U: Gauge, inp, out, nrhs, rho, degree, lo, hi, scale, prec
                                           _stream(stream)))
 
 
+def overlap_dslash(U: Gauge, inp, out, nrhs, rho, mass, degree, lo, hi, scale, dagger=0, prec="f32", recon=12,
+                   stream=None):
+    return _check(lib().overlap_dslash(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(rho),
+                                       float(mass), int(degree), float(lo), float(hi), float(scale), int(dagger),
+                                       _prec(prec), int(recon), _stream(stream)))
+
+
+def overlap_cg(U: Gauge, eta, x, nrhs, rho, mass, degree, lo, hi, scale, tol, maxiter, sloppy="f32", recon=12,
+               delta=1e-3, stream=None, check=True):
+    infos = (WlSolveInfo * int(nrhs))()
+    st = lib().overlap_cg(U.handle, _ptr(eta, "eta"), _ptr(x, "x"), int(nrhs), float(rho), float(mass),
+                          int(degree), float(lo), float(hi), float(scale), float(tol), int(maxiter),
+                          _prec(sloppy), int(recon), float(delta), infos, _stream(stream))
+    res = [i.as_dict() for i in infos]
+    if check:
+        _check(st, res)
+    return st, res
+
+
 def wl_hw2_lmax(U: Gauge, rho, v0, iters, stream=None) -> float:
     r = ctypes.c_double()
     _check(lib().wl_hw2_lmax(U.handle, float(rho), _ptr(v0, "v0"), int(iters), ctypes.byref(r), _stream(stream)))
@@ -233,8 +255,9 @@ def wl_bench_copy(nbytes, reps=20, stream=None) -> float:
     return r.value
 
 
-def wl_prof_enable(on=True):
-    _check(lib().wl_prof_enable(int(bool(on))))
+def wl_prof_enable(on=1):
+    """0: off; 1: time every hop launch; 2: only hops replayed from captured graphs."""
+    _check(lib().wl_prof_enable(int(on)))
 
 
 def wl_prof_select(prec=-1):
