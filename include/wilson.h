@@ -150,6 +150,35 @@ wl_status wilson_cg_multi(int32_t nsys, const wl_gauge *U, const double *const *
                           const int32_t *nrhs, const double *kappa, double tol, int32_t maxiter,
                           wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info, void *stream);
 
+/* ---------------------------------------------------------------- Wilson-clover */
+
+/* The Wilson-clover operator (QUDA_DIRAC_CLOVER of Table 1) in the kappa
+ * normalisation of the hop:  D = A - kappa H,  A(x) = 1 + i kappa c_sw
+ * sum_{m<n} s_mn F_mn(x), s_mn = (i/2)[g_m, g_n], F_mn = (Q_mn - Q_mn^dagger)/8
+ * with Q_mn(x) the four plaquettes of the m-n plane with a corner at x (each a
+ * loop from x, m-direction first).  A is built on the GPU from the handle's
+ * links on first use for each value of kappa c_sw and kept with the handle
+ * (FP64 and FP32 copies of A and A^{-1}: 2 x 864 bytes per site).  c_sw = 0
+ * gives the Wilson operator.  Layouts, streams and errors as for the Wilson
+ * entry points. */
+
+/* out = D in (dagger: A in - kappa H^dagger in) on the whole lattice, nrhs
+ * canonical fields; in and out must not overlap.  Asynchronous on `stream`. */
+wl_status wilson_clover_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double kappa, double csw,
+                               int32_t dagger, wl_prec prec, int32_t recon, void *stream);
+
+/* Solve D psi = eta as wilson_cg / wilson_bicgstab do, on the asymmetric Schur
+ * complement M = A_ee - kappa^2 D_eo A_oo^{-1} D_oe with b' = eta_e +
+ * kappa D_eo A_oo^{-1} eta_o and psi_o = A_oo^{-1} (eta_o + kappa D_oe psi_e);
+ * the stop test and info are those of wilson_cg, with the clover operator.
+ * Synchronises `stream`. */
+wl_status wilson_clover_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double csw,
+                           double tol, int32_t maxiter, wl_prec sloppy, int32_t recon, double delta,
+                           wl_solve_info *info, void *stream);
+wl_status wilson_clover_bicgstab(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double csw,
+                                 double tol, int32_t maxiter, wl_prec sloppy, int32_t recon, double delta,
+                                 wl_solve_info *info, void *stream);
+
 /* ---------------------------------------------------------------- overlap sign */
 
 /* out = eps(H_W) in ~= scale^{-1/2} H_W p(H_W^2 / scale) in on the whole
@@ -221,17 +250,17 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
  * bandwidth reference for the roofline; mean seconds per copy. */
 wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, void *stream);
 
-/* Per-kernel timing of the library's own hop launches.  on = 1: every hop
- * launch is timed -- eager launches are dispatched with start/end HIP events
- * that the dispatch records at the kernel's start and end, and hops captured
- * into a solver's graph get event-record nodes around them, read after every
- * replay (such timed graphs are captured separately from untimed ones).
- * on = 2: only the graph-replayed hops are timed (eager intervals include the
- * dispatch latency).  on = 0: off.  wl_prof_read returns launches, total
- * milliseconds and algorithmic GB of the timed launches since the last read
- * and resets the counters. */
+/* Per-kernel timing of the library's own hop launches: when enabled, every
+ * hop launch outside graph capture drains its stream and is dispatched with
+ * start/end HIP events that the dispatch itself records (dispatch to
+ * completion), and its blocks store readings of the device's constant-rate
+ * steady clock at their start and end, whose span (first block start to last
+ * block end) is the kernel's own duration.  Solvers run without graphs while
+ * timing is on.  wl_prof_read returns launches, total event milliseconds,
+ * algorithmic GB and total kernel milliseconds of the timed launches since
+ * the last read and resets the counters. */
 wl_status wl_prof_enable(int32_t on);
-wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes);
+wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes, double *hop_kernel_ms);
 
 /* Restrict that timing to hop launches of one storage precision (a wl_prec),
  * or -1 for all (the default). */

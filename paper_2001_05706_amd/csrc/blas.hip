@@ -273,6 +273,21 @@ __global__ __launch_bounds__(256) void k_g5copy(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
 }
 
+// y = A^{-1} x at the sites of parity a.parity (FP64 term for FP64 fields,
+// FP32 otherwise); systems without a clover term copy
+template <int P>
+__global__ __launch_bounds__(256) void k_clov_inv(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    constexpr int CP = P == P_F64 ? P_F64 : P_F32;
+    T x[24];
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
+    if (sd.clovinv) clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, x);
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+}
+
 template <int PD, int PS>
 __global__ __launch_bounds__(256) void k_convert(BlasArgs a)
 {
@@ -306,6 +321,7 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
     case BL_BICG_XR: hipLaunchKernelGGL(k_bicg_xr<P>, g, b, 0, s, a); break;
     case BL_CDOT: hipLaunchKernelGGL(k_cdot<P>, g, b, 0, s, a); break;
     case BL_G5COPY: hipLaunchKernelGGL(k_g5copy<P>, g, b, 0, s, a); break;
+    case BL_CLOV_INV: hipLaunchKernelGGL(k_clov_inv<P>, g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,8 +1,12 @@
-// cg.hip -- even-odd preconditioned Krylov solvers for the Wilson operator,
-// mixed precision with FP64 reliable updates, for one set of systems x
-// right-hand sides at once (QUDA_DIRAC_WILSON of Table 1; the mixed-precision
-// inverters of the QUDA line of work cited in Section 1): CG on the normal
-// equations (CGNR) and BiCGStab on the Schur system itself.
+// cg.hip -- even-odd preconditioned Krylov solvers for the Wilson and
+// Wilson-clover operators, mixed precision with FP64 reliable updates, for one
+// set of systems x right-hand sides at once (QUDA_DIRAC_WILSON and
+// QUDA_DIRAC_CLOVER of Table 1; the mixed-precision inverters of the QUDA line
+// of work cited in Section 1): CG on the normal equations (CGNR) and BiCGStab
+// on the Schur system itself.  With a clover term A the Schur operator is the
+// asymmetric M = A_ee - kappa^2 D_eo A_oo^{-1} D_oe (both clover factors sit at
+// output sites, so they ride in the hop epilogues), b' = eta_e +
+// kappa D_eo A_oo^{-1} eta_o and psi_o = A_oo^{-1} (eta_o + kappa D_oe psi_e).
 //
 //   b' = eta_e + kappa D_eo eta_o,   M = 1 - kappa^2 D_eo D_oe,
 //   M^+ = 1 - kappa^2 D_oe^+ D_eo^+ (dagger hops in the same order).
@@ -110,22 +114,27 @@ struct Cg {
         return WL_OK;
     }
 
-    Epi epi(const double *coef, int nx = 0, Field x0 = Field(), Field x1 = Field())
+    Epi epi(const double *coef, int nx = 0, Field x0 = Field(), Field x1 = Field(), int clov = 0)
     {
         Epi e;
         e.coef = coef;
         e.nx = nx;
         e.X[0] = x0;
         e.X[1] = x1;
+        e.clov = clov;
         return e;
     }
+    // the two hops of the Schur operator: t_o = A_oo^{-1} D_oe in, out = A_ee in - kappa^2 D_eo t_o
+    // (A = 1 for systems without a clover term)
+    Epi first(const double *coef) { return epi(coef, 0, Field(), Field(), EPI_CLOV_INV); }
+    Epi second(const double *coef, int nx, Field x0, Field x1 = Field()) { return epi(coef, nx, x0, x1, EPI_CLOV_X0); }
 
     // out = M in (dag = false) or M^+ in (dag = true); tmp is an odd-parity field
     wl_status apply_M(int prec, int rc, bool dag, const Field &out, const Field &in, const Field &tmp,
                       const RedSpec &red, bool use_active = true)
     {
-        WL_TRY(hop(S, prec, rc, dag, 1, tmp, in, epi(c_plain), no_red(), s, use_active));
-        WL_TRY(hop(S, prec, rc, dag, 0, out, tmp, epi(c_M, 1, in), red, s, use_active));
+        WL_TRY(hop(S, prec, rc, dag, 1, tmp, in, first(c_plain), no_red(), s, use_active));
+        WL_TRY(hop(S, prec, rc, dag, 0, out, tmp, second(c_M, 1, in), red, s, use_active));
         return WL_OK;
     }
 
@@ -134,8 +143,8 @@ struct Cg {
     // final true residual always uses all 18.
     wl_status residual64(bool use_active = true)
     {
-        WL_TRY(hop(S, P_F64, recon, false, 1, t64, xh, epi(c_plain), no_red(), s, use_active));
-        WL_TRY(hop(S, P_F64, recon, false, 0, rh, t64, epi(c_res, 2, xh, bp),
+        WL_TRY(hop(S, P_F64, recon, false, 1, t64, xh, first(c_plain), no_red(), s, use_active));
+        WL_TRY(hop(S, P_F64, recon, false, 0, rh, t64, second(c_res, 2, xh, bp),
                    red_spec(S, RED_STORE, S.scal(SC_RR)), s, use_active));
         return WL_OK;
     }
@@ -148,13 +157,13 @@ struct Cg {
             // t = M s, omega = <t, s> / |t|^2;  x += alpha p + omega s;  r = s - omega t, rho = <rhat, r>
             Field fp[3] = {p, rl, q};
             WL_TRY(blas(S, BL_BICG_P, sloppy, fp, 3, nullptr, no_red(), s));
-            WL_TRY(hop(S, sloppy, recon, false, 1, tl, p, epi(c_plain), no_red(), s));
-            WL_TRY(hop(S, sloppy, recon, false, 0, q, tl, epi(c_M, 2, p, rhat),
+            WL_TRY(hop(S, sloppy, recon, false, 1, tl, p, first(c_plain), no_red(), s));
+            WL_TRY(hop(S, sloppy, recon, false, 0, q, tl, second(c_M, 2, p, rhat),
                        red_spec(S, RED_BICG_ALPHA, nullptr, 2, RM_DOT_X1), s));
             Field fs[3] = {sv, rl, q};
             WL_TRY(blas(S, BL_BICG_S, sloppy, fs, 3, nullptr, no_red(), s));
-            WL_TRY(hop(S, sloppy, recon, false, 1, tl, sv, epi(c_plain), no_red(), s));
-            WL_TRY(hop(S, sloppy, recon, false, 0, tb, tl, epi(c_M, 1, sv),
+            WL_TRY(hop(S, sloppy, recon, false, 1, tl, sv, first(c_plain), no_red(), s));
+            WL_TRY(hop(S, sloppy, recon, false, 0, tb, tl, second(c_M, 1, sv),
                        red_spec(S, RED_BICG_OMEGA, nullptr, 3, RM_OUT_X0), s));
             Field fx[6] = {xl, p, sv, rl, tb, rhat};
             WL_TRY(blas(S, BL_BICG_XR, sloppy, fx, 6, nullptr, red_spec(S, RED_BICG_RHO, hist_row, 3), s));
@@ -224,14 +233,12 @@ struct Cg {
 
     wl_status chunk(int k)
     {
-        if (!use_graphs) {
+        if (!use_graphs || prof().on) {
             for (int j = 0; j < k; ++j) WL_TRY(iteration(S.hist + (size_t)j * S.nvec));
             return WL_OK;
         }
-        // a timed graph carries event-record nodes around its hops: it is a graph of its own
-        Prof &P = prof();
         const std::string key = "cg/" + std::to_string(method) + "/" + std::to_string(k) + "/" +
-                                std::to_string(sloppy) + "/" + std::to_string(recon) + (P.on ? "/timed" : "");
+                                std::to_string(sloppy) + "/" + std::to_string(recon);
         auto it = S.graphs.find(key);
         if (it == S.graphs.end()) {
             const SysDesc *tab = nullptr;  // packed links and tables exist before capture
@@ -241,14 +248,11 @@ struct Cg {
             const double saved = g_bytes_acc;
             hipStream_t user = s;
             s = cs;
-            EventList evl;
-            if (P.on) P.capture = &evl;
             WL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
             wl_status st = WL_OK;
             for (int j = 0; j < k && st == WL_OK; ++j) st = iteration(S.hist + (size_t)j * S.nvec);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(cs, &g);
-            P.capture = nullptr;
             s = user;
             g_bytes_acc = saved;
             if (st != WL_OK) {
@@ -261,14 +265,9 @@ struct Cg {
             (void)hipGraphDestroy(g);
             if (ie != hipSuccess) return set_error(WL_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
             it = S.graphs.emplace(key, ex).first;
-            if (P.on) P.graph[(const void *)ex] = std::move(evl);
         }
         g_bytes_acc += k * iteration_bytes();
         WL_HIP(hipGraphLaunch(it->second, s));
-        if (P.on) {
-            auto ev = P.graph.find((const void *)it->second);
-            P.replayed = ev == P.graph.end() ? nullptr : &ev->second;
-        }
         return WL_OK;
     }
 };
@@ -316,7 +315,14 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
     WL_TRY(pack(S, eta, 1, cg.eta_o, s));
     WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_e, 1, nullptr, red_spec(S, RED_STORE, S.scal(SC_ETA)), s));
     WL_TRY(blas(S, BL_NORM2, P_F64, &cg.eta_o, 1, nullptr, red_spec(S, RED_ACCUM, S.scal(SC_ETA)), s));
-    WL_TRY(hop(S, P_F64, 18, false, 0, cg.bp, cg.eta_o, cg.epi(cg.c_bp, 1, cg.eta_e), no_red(), s));
+    // b' = eta_e + kappa D_eo A_oo^{-1} eta_o (xo holds A_oo^{-1} eta_o until psi_o is formed)
+    Field src_o = cg.eta_o;
+    if (S.has_clover) {
+        const Field f[2] = {cg.xo, cg.eta_o};
+        WL_TRY(blas(S, BL_CLOV_INV, P_F64, f, 2, nullptr, no_red(), s, true, 1));
+        src_o = cg.xo;
+    }
+    WL_TRY(hop(S, P_F64, 18, false, 0, cg.bp, src_o, cg.epi(cg.c_bp, 1, cg.eta_e), no_red(), s));
     WL_TRY(pack(S, (const double *const *)x, 0, cg.xh, s));
     WL_TRY(cg.residual64());
     WL_HIP(hipMemcpyAsync(hp, S.sc, sizeof(double) * ExecSet::SC_N * nv, hipMemcpyDeviceToHost, s));
@@ -415,7 +421,6 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
             int32_t *hbad = (int32_t *)(hp + (size_t)ExecSet::kHist * nv);
             WL_HIP(hipMemcpyAsync(hbad, S.bad, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, s));
             WL_HIP(hipStreamSynchronize(s));
-            prof_collect_graph();  // a replayed graph's events are read before its next replay
             if (trace) {
                 double sc[ExecSet::SC_N];
                 for (int j = 0; j < ExecSet::SC_N; ++j)
@@ -557,10 +562,11 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
     // odd sites, true residual with the whole-lattice operator, unpack
     std::fill(S.h_active.begin(), S.h_active.end(), 1);
     WL_TRY(S.upload_active(s));
-    WL_TRY(hop(S, P_F64, 18, false, 1, cg.xo, cg.xh, cg.epi(cg.c_bp, 1, cg.eta_o), no_red(), s));
-    WL_TRY(hop(S, P_F64, 18, false, 0, cg.rh, cg.xo, cg.epi(cg.c_tres, 2, cg.xh, cg.eta_e),
+    // psi_o = A_oo^{-1} (eta_o + kappa D_oe psi_e); true residual eta - (A - kappa H) psi per parity
+    WL_TRY(hop(S, P_F64, 18, false, 1, cg.xo, cg.xh, cg.epi(cg.c_bp, 1, cg.eta_o, Field(), EPI_CLOV_INV), no_red(), s));
+    WL_TRY(hop(S, P_F64, 18, false, 0, cg.rh, cg.xo, cg.epi(cg.c_tres, 2, cg.xh, cg.eta_e, EPI_CLOV_X0),
                red_spec(S, RED_STORE, S.scal(SC_RR)), s));
-    WL_TRY(hop(S, P_F64, 18, false, 1, cg.t64, cg.xh, cg.epi(cg.c_tres, 2, cg.xo, cg.eta_o),
+    WL_TRY(hop(S, P_F64, 18, false, 1, cg.t64, cg.xh, cg.epi(cg.c_tres, 2, cg.xo, cg.eta_o, EPI_CLOV_X0),
                red_spec(S, RED_ACCUM, S.scal(SC_RR)), s));
     WL_TRY(unpack(S, x, 0, cg.xh, s));
     WL_TRY(unpack(S, x, 1, cg.xo, s));
@@ -639,6 +645,39 @@ wl_status wilson_bicgstab(wl_gauge U, const double *eta, double *x, int32_t nrhs
     const double *e[1] = {eta};
     double *xx[1] = {x};
     return run_cg(*S, e, xx, recon, tol, maxiter, sloppy, delta, info, (hipStream_t)stream, M_BICGSTAB);
+}
+
+static wl_status clover_solve(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double csw,
+                              double tol, int32_t maxiter, wl_prec sloppy, int32_t recon, double delta,
+                              wl_solve_info *info, void *stream, int method)
+{
+    clear_error();
+    WL_TRY(check_gauge(U));
+    if (nrhs < 1) return set_error(WL_ERR_ARG, "nrhs = %d must be >= 1", nrhs);
+    if (!(kappa > 0) || !std::isfinite(kappa)) return set_error(WL_ERR_ARG, "kappa must be > 0 and finite");
+    if (!(csw >= 0) || !std::isfinite(csw)) return set_error(WL_ERR_ARG, "c_sw must be >= 0 and finite");
+    WL_TRY(check_solver_args(tol, maxiter, sloppy, recon, delta));
+    WL_TRY(check_field(eta, U, nrhs, "eta"));
+    WL_TRY(check_field(x, U, nrhs, "x"));
+    ExecSet *S = nullptr;
+    WL_TRY(get_set({SysEntry{U, nrhs, kappa, csw}}, &S));
+    const double *e[1] = {eta};
+    double *xx[1] = {x};
+    return run_cg(*S, e, xx, recon, tol, maxiter, sloppy, delta, info, (hipStream_t)stream, method);
+}
+
+wl_status wilson_clover_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double csw,
+                           double tol, int32_t maxiter, wl_prec sloppy, int32_t recon, double delta,
+                           wl_solve_info *info, void *stream)
+{
+    return clover_solve(U, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy, recon, delta, info, stream, M_CGNR);
+}
+
+wl_status wilson_clover_bicgstab(wl_gauge U, const double *eta, double *x, int32_t nrhs, double kappa, double csw,
+                                 double tol, int32_t maxiter, wl_prec sloppy, int32_t recon, double delta,
+                                 wl_solve_info *info, void *stream)
+{
+    return clover_solve(U, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy, recon, delta, info, stream, M_BICGSTAB);
 }
 
 wl_status wilson_cg_multi(int32_t nsys, const wl_gauge *U, const double *const *eta, double *const *x,

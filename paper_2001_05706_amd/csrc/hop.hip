@@ -19,14 +19,24 @@ namespace wl {
 //   fence: directions whose operands may be in flight together per wave
 //   waves: occupancy target (waves per SIMD), which caps registers at 512/waves
 //   nt:    non-temporal link loads (links used once) or cached (shared by RHS)
+//   0: fence 2, 4 waves (FP64: 2), non-temporal links
+//   1: fence 1, 5 waves (FP64: 3), non-temporal links
+//   2: fence 1, 6 waves (FP64: 3), non-temporal links
+//   3: fence 2, 4 waves (FP64: 2), cached links
+//   4: fence 4, 4 waves, cached links -- twice the bytes in flight per wave
+//   5: fence 4, 5 waves, cached links
+// Variants 4 and 5 exist for FP16/BF16 storage only (FP32 and FP64 operands of
+// four directions do not fit the registers); for those they repeat variant 3.
 template <int SP, int VAR> struct HopVar {
-    static constexpr int fence = VAR == 0 || VAR == 3 ? 2 : 1;
-    static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR == 3 ? 2 : 3) : (VAR == 0 || VAR == 3 ? 4 : VAR == 1 ? 5 : 6);
-    static constexpr bool nt = VAR != 3;
+    static constexpr bool half = SP == P_F16 || SP == P_BF16;
+    static constexpr int fence = VAR == 0 || VAR == 3 ? 2 : (VAR >= 4 ? (half ? 4 : 2) : 1);
+    static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR >= 3 ? 2 : 3)
+                                             : (VAR == 0 || VAR == 3 || VAR == 4 ? 4 : VAR == 2 ? 6 : 5);
+    static constexpr bool nt = VAR < 3;
 };
-constexpr int kHopVariants = 4;
+constexpr int kHopVariants = 6;
 
-template <int SP, int GP, int R, bool DAG, int VAR>
+template <int SP, int GP, int R, bool DAG, int VAR, bool CLOV>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves))) void k_hop(HopArgs a)
 {
     using T = typename SpinorFmt<SP>::real;
@@ -36,6 +46,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     const int lb = xcd_remap(blockIdx.x, a.nblocks);
     const BlkMap bm = a.map[lb];
     if (a.active && !a.active[bm.v]) return;
+    const unsigned long long t_start = a.stamps ? (unsigned long long)wall_clock64() : 0ull;
     const VecDesc vd = a.vec[bm.v];
     const SysDesc sd = a.sys[vd.sys];
     const int cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
@@ -54,11 +65,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
 
         const double *cf = a.epi.coef + vd.sys * 5;
         const T c = (T)cf[4];
+        // clover term of this system at the output site (FP16/BF16 launches use the FP32 copy)
+        constexpr int CP = SP == P_F64 ? P_F64 : P_F32;
+        const bool clov = CLOV && a.epi.clov != 0 && sd.clov != nullptr;
         T o[24];
         if (a.epi.nx >= 1) {
             T x[24];
             load_spinor<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
                             sd.stride, cb, x);
+            if constexpr (CLOV) {
+                if (clov && (a.epi.clov & EPI_CLOV_X0))
+                    clover_apply<CP>(clover_parity<CP>(sd.clov, a.parity, sd.stride), sd.stride, cb, x);
+            }
             const T a0 = (T)cf[0];
 #pragma unroll
             for (int k = 0; k < 24; ++k) o[k] = a0 * x[k] + c * acc[k];
@@ -69,6 +87,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
         if (a.epi.g5) {
 #pragma unroll
             for (int k = 12; k < 24; ++k) o[k] = -o[k];
+        }
+        if constexpr (CLOV) {
+            if (clov && (a.epi.clov & EPI_CLOV_INV))
+                clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, o);
         }
         for (int j = 1; j < a.epi.nx; ++j) {
             T x[24];
@@ -98,6 +120,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
         }
     }
     if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+    if (a.stamps) {
+        // the block's work ends when its last wave ends
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.stamps[2 * lb] = t_start;
+            a.stamps[2 * lb + 1] = (unsigned long long)wall_clock64();
+        }
+    }
 }
 
 // With events, the dispatch itself records them at the kernel's start and end
@@ -113,39 +143,47 @@ static void dispatch(K kernel, const HopArgs &a, int block, hipStream_t s, hipEv
 }
 
 template <int SP, int GP, int R, int VAR>
-static hipError_t launch_hop_v(bool dag, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+static hipError_t launch_hop_v(bool dag, bool clov, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1)
 {
-    if (dag)
-        dispatch(k_hop<SP, GP, R, true, VAR>, a, block, s, e0, e1);
+    // the clover epilogue is a separate instantiation: it needs registers the Wilson kernels do not
+    if (dag && clov)
+        dispatch(k_hop<SP, GP, R, true, VAR, true>, a, block, s, e0, e1);
+    else if (dag)
+        dispatch(k_hop<SP, GP, R, true, VAR, false>, a, block, s, e0, e1);
+    else if (clov)
+        dispatch(k_hop<SP, GP, R, false, VAR, true>, a, block, s, e0, e1);
     else
-        dispatch(k_hop<SP, GP, R, false, VAR>, a, block, s, e0, e1);
+        dispatch(k_hop<SP, GP, R, false, VAR, false>, a, block, s, e0, e1);
     return hipGetLastError();
 }
 
 template <int SP, int GP, int R>
-static hipError_t launch_hop_t(int var, bool dag, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0,
-                               hipEvent_t e1)
+static hipError_t launch_hop_t(int var, bool dag, bool clov, const HopArgs &a, int block, hipStream_t s,
+                               hipEvent_t e0, hipEvent_t e1)
 {
     switch (var) {
-    case 0: return launch_hop_v<SP, GP, R, 0>(dag, a, block, s, e0, e1);
-    case 1: return launch_hop_v<SP, GP, R, 1>(dag, a, block, s, e0, e1);
-    case 2: return launch_hop_v<SP, GP, R, 2>(dag, a, block, s, e0, e1);
-    case 3: return launch_hop_v<SP, GP, R, 3>(dag, a, block, s, e0, e1);
+    case 0: return launch_hop_v<SP, GP, R, 0>(dag, clov, a, block, s, e0, e1);
+    case 1: return launch_hop_v<SP, GP, R, 1>(dag, clov, a, block, s, e0, e1);
+    case 2: return launch_hop_v<SP, GP, R, 2>(dag, clov, a, block, s, e0, e1);
+    case 3: return launch_hop_v<SP, GP, R, 3>(dag, clov, a, block, s, e0, e1);
+    case 4: return launch_hop_v<SP, GP, R, 4>(dag, clov, a, block, s, e0, e1);
+    case 5: return launch_hop_v<SP, GP, R, 5>(dag, clov, a, block, s, e0, e1);
     }
     return hipErrorInvalidValue;
 }
 
-int hop_variants() { return kHopVariants; }
+int hop_variants(int prec) { return prec == P_F16 || prec == P_BF16 ? kHopVariants : 4; }
 
-hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s,
+hipError_t launch_hop(int prec, int recon, bool dag, bool clov, int var, const HopArgs &a, int block, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1)
 {
-    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(var, dag, a, block, s, e0, e1);
-    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(var, dag, a, block, s, e0, e1);
-    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(var, dag, a, block, s, e0, e1);
-    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(var, dag, a, block, s, e0, e1);
-    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(var, dag, a, block, s, e0, e1);
-    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(var, dag, a, block, s, e0, e1);
+    if (prec == P_F64 && recon == 18) return launch_hop_t<P_F64, P_F64, 18>(var, dag, clov, a, block, s, e0, e1);
+    if (prec == P_F64 && recon == 12) return launch_hop_t<P_F64, P_F64, 12>(var, dag, clov, a, block, s, e0, e1);
+    if (prec == P_F32 && recon == 18) return launch_hop_t<P_F32, P_F32, 18>(var, dag, clov, a, block, s, e0, e1);
+    if (prec == P_F32 && recon == 12) return launch_hop_t<P_F32, P_F32, 12>(var, dag, clov, a, block, s, e0, e1);
+    if (prec == P_F16 && recon == 12) return launch_hop_t<P_F16, P_F16, 12>(var, dag, clov, a, block, s, e0, e1);
+    if (prec == P_BF16 && recon == 12) return launch_hop_t<P_BF16, P_BF16, 12>(var, dag, clov, a, block, s, e0, e1);
     return hipErrorInvalidValue;
 }
 

@@ -113,25 +113,6 @@ void prof_collect()
     }
     p.pending.ev.clear();
     p.pending.gbytes.clear();
-    prof_collect_graph();
-}
-
-void prof_collect_graph()
-{
-    Prof &p = prof();
-    if (!p.replayed) return;
-    const EventList &L = *p.replayed;
-    for (size_t i = 0; i < L.ev.size(); ++i) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, L.ev[i].first, L.ev[i].second) == hipSuccess) {
-            p.ms += ms;
-            p.launches += 1;
-            p.gbytes += L.gbytes[i];
-        } else {
-            (void)hipGetLastError();
-        }
-    }
-    p.replayed = nullptr;
 }
 
 bool capturing(hipStream_t s)
@@ -211,6 +192,11 @@ wl_gauge_s::~wl_gauge_s()
     (void)hipFree(U);
     for (auto &a : packed)
         for (auto &p : a) (void)hipFree(p);
+    for (auto &c : clovers)
+        for (int k = 0; k < 2; ++k) {
+            (void)hipFree(c.A[k]);
+            (void)hipFree(c.Ainv[k]);
+        }
 }
 
 namespace wl {
@@ -235,25 +221,50 @@ wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const voi
     return WL_OK;
 }
 
+wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const void **A, const void **Ainv)
+{
+    const int k = prec == P_F64 ? 0 : 1;
+    for (auto &c : g->clovers)
+        if (c.kc == kc) {
+            *A = c.A[k];
+            *Ainv = c.Ainv[k];
+            return WL_OK;
+        }
+    if (capturing(s)) return set_error(WL_ERR_HIP, "clover term first needed inside a graph capture");
+    wl_gauge_s::Clover c{kc, {nullptr, nullptr}, {nullptr, nullptr}};
+    const size_t per = (size_t)2 * g->geom.stride * 72;  // reals of one field, both parities
+    bool ok = true;
+    for (int j = 0; j < 2 && ok; ++j) {
+        const size_t bytes = per * (j == 0 ? sizeof(double) : sizeof(float));
+        ok = hipMalloc(&c.A[j], bytes) == hipSuccess && hipMalloc(&c.Ainv[j], bytes) == hipSuccess;
+        if (ok) ok = hipMemsetAsync(c.A[j], 0, bytes, s) == hipSuccess && hipMemsetAsync(c.Ainv[j], 0, bytes, s) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        for (int j = 0; j < 2; ++j) {
+            (void)hipFree(c.A[j]);
+            (void)hipFree(c.Ainv[j]);
+        }
+        return set_error(WL_ERR_NOMEM, "cannot allocate the clover term");
+    }
+    g->clovers.push_back(c);
+    WL_HIP(launch_clover_build(g->U, g->geom, kc, c.A[0], c.A[1], s));
+    WL_HIP(launch_clover_invert(g->geom, c.A[0], c.Ainv[0], c.Ainv[1], s));
+    *A = c.A[k];
+    *Ainv = c.Ainv[k];
+    return WL_OK;
+}
+
 // ------------------------------------------------------------------ execution sets
 
-ExecSet::ExecSet(const std::vector<SysEntry> &s) : systems(s) {}
+ExecSet::ExecSet(const std::vector<SysEntry> &s) : systems(s)
+{
+    for (auto &e : systems) has_clover = has_clover || e.csw != 0.0;
+}
 
 ExecSet::~ExecSet()
 {
-    Prof &P = prof();
-    for (auto &kv : graphs) {
-        auto ev = P.graph.find((const void *)kv.second);
-        if (ev != P.graph.end()) {
-            if (P.replayed == &ev->second) P.replayed = nullptr;
-            for (auto &e : ev->second.ev) {
-                (void)hipEventDestroy(e.first);
-                (void)hipEventDestroy(e.second);
-            }
-            P.graph.erase(ev);
-        }
-        (void)hipGraphExecDestroy(kv.second);
-    }
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : fields) {
         (void)hipFree(kv.second.p);
         (void)hipFree(kv.second.n);
@@ -344,7 +355,10 @@ wl_status ExecSet::sys_table(int prec, int recon, hipStream_t s, const SysDesc *
     for (size_t i = 0; i < systems.size(); ++i) {
         h[i] = systems[i].g->geom;
         h[i].gauge = nullptr;  // prec < 0: geometry only
-        if (prec >= 0) WL_TRY(gauge_packed(systems[i].g, prec, recon, s, &h[i].gauge));
+        h[i].clov = h[i].clovinv = nullptr;
+        if (prec >= 0 && recon != 0) WL_TRY(gauge_packed(systems[i].g, prec, recon, s, &h[i].gauge));
+        if (prec >= 0 && systems[i].csw != 0.0)
+            WL_TRY(gauge_clover(systems[i].g, systems[i].kappa * systems[i].csw, prec, s, &h[i].clov, &h[i].clovinv));
     }
     SysDesc *d = nullptr;
     WL_ALLOC(d, sizeof(SysDesc) * h.size());
@@ -427,7 +441,10 @@ wl_status get_set(const std::vector<SysEntry> &systems, ExecSet **out)
         if (S->systems.size() != systems.size()) continue;
         bool same = true;
         for (size_t i = 0; i < systems.size() && same; ++i)
-            same = S->systems[i].g == systems[i].g && S->systems[i].nrhs == systems[i].nrhs;
+            same = S->systems[i].g == systems[i].g && S->systems[i].nrhs == systems[i].nrhs &&
+                   S->systems[i].csw == systems[i].csw &&
+                   // the clover term of a set's descriptor tables depends on kappa
+                   (systems[i].csw == 0.0 || S->systems[i].kappa == systems[i].kappa);
         if (same) {
             for (size_t i = 0; i < systems.size(); ++i) S->systems[i].kappa = systems[i].kappa;
             *out = S.get();
@@ -509,6 +526,16 @@ double hop_bytes(const ExecSet &S, int prec, int recon, bool use_active)
     return b;
 }
 
+double clover_bytes(const ExecSet &S, int prec, bool use_active)
+{
+    // 72 reals per site, FP64 for FP64 launches and FP32 otherwise, shared by the RHS of a system
+    const double site = 72.0 * (prec == P_F64 ? 8 : 4);
+    double b = 0;
+    for (size_t i = 0; i < S.systems.size(); ++i)
+        if (S.systems[i].csw != 0.0 && any_active_in(S, (int)i, use_active)) b += site * S.systems[i].g->geom.Vh;
+    return b;
+}
+
 double blas_bytes(const ExecSet &S, int prec, int passes, bool use_active)
 {
     double b = 0;
@@ -529,10 +556,10 @@ std::string hop_key(const ExecSet &S, int prec, int recon, bool dag)
 }
 
 // (variant, block size) pairs encoded as variant * 1024 + block
-std::vector<int> hop_candidates()
+std::vector<int> hop_candidates(int prec)
 {
     std::vector<int> c;
-    for (int v = 0; v < hop_variants(); ++v)
+    for (int v = 0; v < hop_variants(prec); ++v)
         for (int b : {64, 128, 256, 512}) c.push_back(v * 1024 + b);
     return c;
 }
@@ -540,6 +567,7 @@ std::vector<int> hop_candidates()
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
               const RedSpec &red, hipStream_t s, bool use_active)
 {
+    const bool clov = e.clov != 0 && S.has_clover;
     const SysDesc *sysd = nullptr;
     WL_TRY(S.sys_table(prec, recon, s, &sysd));
     auto mk = [&](const Layout *L, const RedSpec &rs) {
@@ -556,6 +584,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         a.out_norm = out.n;
         a.epi.nx = e.nx;
         a.epi.g5 = e.g5;
+        a.epi.clov = clov ? e.clov : 0;
         a.epi.coef = e.coef;
         for (int j = 0; j < 4; ++j) {
             a.epi.X[j] = e.X[j].p;
@@ -564,40 +593,63 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         a.red = rs;
         return a;
     };
-    const std::string key = hop_key(S, prec, recon, dag);
-    const int cfg = tuned_block(key, hop_candidates(), s, [&](int c) -> hipError_t {
+    const std::string key = hop_key(S, prec, recon, dag) + (clov ? "/clov" : "");
+    std::vector<int> cands = hop_candidates(prec);
+    if (clov)  // the clover epilogue needs the registers of the two-direction variants (0 and 3)
+        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 == 1 || c / 1024 == 2; }),
+                    cands.end());
+    if (cands.empty()) cands = hop_candidates(prec);
+    const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;
         if (S.layout(c % 1024, &L) != WL_OK) return hipErrorOutOfMemory;
-        return launch_hop(prec, recon, dag, c / 1024, mk(L, no_red()), c % 1024, s);
+        return launch_hop(prec, recon, dag, clov, c / 1024, mk(L, no_red()), c % 1024, s);
     });
     const int B = cfg % 1024, var = cfg / 1024;
     const Layout *L = nullptr;
     WL_TRY(S.layout(B, &L));
-    const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active);
+    const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active) +
+                         (clov ? ((e.clov & EPI_CLOV_X0) ? 1 : 0) + ((e.clov & EPI_CLOV_INV) ? 1 : 0) : 0) *
+                             clover_bytes(S, prec, use_active);
     g_bytes_acc += bytes;
     Prof &P = prof();
-    const bool want = P.on && (P.prec < 0 || P.prec == prec);
-    const bool cap = capturing(s);
-    if (want && cap && P.capture) {
-        // event-record nodes around the hop node of the graph being captured
+    if (P.on && (P.prec < 0 || P.prec == prec) && !capturing(s)) {
+        // The dispatch records the events at its own start and end; the stream
+        // is drained first so that the packet does not wait behind a running
+        // kernel.  The blocks' steady-clock stamps give the kernel's own span.
         hipEvent_t e0 = nullptr, e1 = nullptr;
         WL_HIP(hipEventCreate(&e0));
         WL_HIP(hipEventCreate(&e1));
-        WL_HIP(hipEventRecord(e0, s));
-        WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
-        WL_HIP(hipEventRecord(e1, s));
-        P.capture->ev.push_back({e0, e1});
-        P.capture->gbytes.push_back(bytes * 1e-9);
-    } else if (want && !cap && !P.graphs_only) {
-        // the dispatch records the events at the kernel's start and end
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        WL_HIP(hipEventCreate(&e0));
-        WL_HIP(hipEventCreate(&e1));
-        WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s, e0, e1));
+        const size_t ns = 2 * (size_t)L->nblocks;
+        if (P.nstamps < ns) {
+            if (P.d_stamps) WL_HIP(hipFree(P.d_stamps));
+            WL_ALLOC(P.d_stamps, ns * sizeof(unsigned long long));
+            P.nstamps = ns;
+            P.h_stamps.resize(ns);
+        }
+        if (P.clock_khz <= 0) {
+            int dev = 0, khz = 0;
+            WL_HIP(hipGetDevice(&dev));
+            WL_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            P.clock_khz = khz;
+        }
+        WL_HIP(hipMemsetAsync(P.d_stamps, 0, ns * sizeof(unsigned long long), s));
+        WL_HIP(hipStreamSynchronize(s));
+        HopArgs ha = mk(L, red);
+        ha.stamps = P.d_stamps;
+        WL_HIP(launch_hop(prec, recon, dag, clov, var, ha, B, s, e0, e1));
+        WL_HIP(hipMemcpyAsync(P.h_stamps.data(), P.d_stamps, ns * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        WL_HIP(hipStreamSynchronize(s));
+        unsigned long long t0 = ~0ull, t1 = 0;
+        for (size_t b = 0; b < ns; b += 2)
+            if (P.h_stamps[b + 1] != 0) {  // blocks of inactive vectors leave their slots at zero
+                t0 = std::min(t0, P.h_stamps[b]);
+                t1 = std::max(t1, P.h_stamps[b + 1]);
+            }
+        if (t1 > t0 && P.clock_khz > 0) P.kernel_ms += (double)(t1 - t0) / P.clock_khz;
         P.pending.ev.push_back({e0, e1});
         P.pending.gbytes.push_back(bytes * 1e-9);
     } else {
-        WL_HIP(launch_hop(prec, recon, dag, var, mk(L, red), B, s));
+        WL_HIP(launch_hop(prec, recon, dag, clov, var, mk(L, red), B, s));
     }
     if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, use_active ? S.d_active : nullptr, S.nvec, s));
     return WL_OK;
@@ -606,10 +658,13 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
 static const int kBlasBlock = 256;
 
 wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
-               hipStream_t s, bool use_active)
+               hipStream_t s, bool use_active, int parity)
 {
     const SysDesc *sysd = nullptr;
-    WL_TRY(S.sys_table(-1, 0, s, &sysd));  // geometry only
+    if (op == BL_CLOV_INV)
+        WL_TRY(S.sys_table(prec, 0, s, &sysd));  // geometry and clover term, no links
+    else
+        WL_TRY(S.sys_table(-1, 0, s, &sysd));  // geometry only
     const Layout *L = nullptr;
     WL_TRY(S.layout(kBlasBlock, &L));
     BlasArgs a{};
@@ -626,7 +681,9 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.sc = S.sc;
     a.nvec = S.nvec;
     a.red = red;
-    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2};
+    a.parity = parity;
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2, 2};
+    if (op == BL_CLOV_INV) g_bytes_acc += clover_bytes(S, prec, use_active);
     if (op == BL_ACCUM)
         g_bytes_acc += blas_bytes(S, P_F64, 2, use_active) + blas_bytes(S, prec, 2, use_active);
     else
@@ -821,7 +878,7 @@ wl_status wilson_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs,
     if (parity >= 0) {
         WL_TRY(coef_table(*S, {0, 0, 0, 0, 1.0}, &e.coef));
         WL_TRY(pack(*S, cin, 1 - parity, fi[1 - parity], s));
-        WL_TRY(hop(*S, prec, recon, dagger, parity, fo[parity], fi[1 - parity], e, no_red(), s));
+        WL_TRY(hop(*S, prec, recon, dagger, parity, fo[parity], fi[1 - parity], e, no_red(), s, false));
         WL_TRY(unpack(*S, cout, parity, fo[parity], s));
         WL_TRY(zero_canon(*S, cout, 1 - parity, s));
     } else {
@@ -830,7 +887,7 @@ wl_status wilson_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs,
         for (int p = 0; p < 2; ++p) WL_TRY(pack(*S, cin, p, fi[p], s));
         for (int p = 0; p < 2; ++p) {
             e.X[0] = fi[p];
-            WL_TRY(hop(*S, prec, recon, dagger, p, fo[p], fi[1 - p], e, no_red(), s));
+            WL_TRY(hop(*S, prec, recon, dagger, p, fo[p], fi[1 - p], e, no_red(), s, false));
         }
         for (int p = 0; p < 2; ++p) WL_TRY(unpack(*S, cout, p, fo[p], s));
     }
@@ -843,13 +900,50 @@ double wl_hop_bytes_per_site(wl_prec prec, int32_t recon, int32_t nrhs)
     return 8.0 * link_bytes(prec, recon) / nrhs + 2.0 * spinor_site_bytes(prec);
 }
 
+wl_status wilson_clover_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double kappa, double csw,
+                               int32_t dagger, wl_prec prec, int32_t recon, void *stream)
+{
+    clear_error();
+    WL_TRY(check_gauge(U));
+    if (nrhs < 1) return set_error(WL_ERR_ARG, "nrhs = %d must be >= 1", nrhs);
+    if (!(kappa > 0) || !std::isfinite(kappa)) return set_error(WL_ERR_ARG, "kappa must be > 0 and finite");
+    if (!(csw >= 0) || !std::isfinite(csw)) return set_error(WL_ERR_ARG, "c_sw must be >= 0 and finite");
+    if (!prec_recon_ok(prec, recon)) return set_error(WL_ERR_PREC, "unsupported precision %d / recon %d", prec, recon);
+    WL_TRY(check_field(in, U, nrhs, "in"));
+    WL_TRY(check_field(out, U, nrhs, "out"));
+    const size_t bytes = (size_t)nrhs * 2 * U->geom.Vh * 24 * sizeof(double);
+    if ((const char *)in < (const char *)out + bytes && (const char *)out < (const char *)in + bytes)
+        return set_error(WL_ERR_ARG, "in and out overlap");
+    hipStream_t s = (hipStream_t)stream;
+    ExecSet *S = nullptr;
+    WL_TRY(get_set({SysEntry{U, nrhs, kappa, csw}}, &S));
+    Field fi[2], fo[2];
+    for (int p = 0; p < 2; ++p) {
+        WL_TRY(S->field("dsl_in" + std::to_string(p), prec, &fi[p]));
+        WL_TRY(S->field("dsl_out" + std::to_string(p), prec, &fo[p]));
+    }
+    const double *cin[1] = {in};
+    double *cout[1] = {out};
+    // out_p = A in_p - kappa hop(in)_p
+    Epi e;
+    WL_TRY(coef_table(*S, {1.0, 0, 0, 0, -kappa}, &e.coef));
+    e.nx = 1;
+    e.clov = EPI_CLOV_X0;
+    for (int p = 0; p < 2; ++p) WL_TRY(pack(*S, cin, p, fi[p], s));
+    for (int p = 0; p < 2; ++p) {
+        e.X[0] = fi[p];
+        // every vector, whatever mask an earlier solve on this set left behind
+        WL_TRY(hop(*S, prec, recon, dagger, p, fo[p], fi[1 - p], e, no_red(), s, false));
+    }
+    for (int p = 0; p < 2; ++p) WL_TRY(unpack(*S, cout, p, fo[p], s));
+    return WL_OK;
+}
+
 wl_status wl_prof_enable(int32_t on)
 {
     clear_error();
-    if (on < 0 || on > 2) return set_error(WL_ERR_ARG, "on must be 0, 1 or 2");
     Prof &P = prof();
     P.on = on != 0;
-    P.graphs_only = on == 2;
     return WL_OK;
 }
 
@@ -861,7 +955,7 @@ wl_status wl_prof_select(int32_t prec)
     return WL_OK;
 }
 
-wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes)
+wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes, double *hop_kernel_ms)
 {
     clear_error();
     prof_collect();
@@ -869,8 +963,10 @@ wl_status wl_prof_read(int64_t *hop_launches, double *hop_ms, double *hop_gbytes
     if (hop_launches) *hop_launches = P.launches;
     if (hop_ms) *hop_ms = P.ms;
     if (hop_gbytes) *hop_gbytes = P.gbytes;
+    if (hop_kernel_ms) *hop_kernel_ms = P.kernel_ms;
     P.launches = 0;
     P.ms = 0.0;
+    P.kernel_ms = 0.0;
     P.gbytes = 0.0;
     return WL_OK;
 }
@@ -933,7 +1029,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
         Epi e;
         e.coef = coef;
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
-        cfg = tuned_block(hop_key(*S, prec, recon, false), hop_candidates(), s, [](int) { return hipSuccess; });
+        cfg = tuned_block(hop_key(*S, prec, recon, false), hop_candidates(prec), s, [](int) { return hipSuccess; });
         B = cfg % 1024;
         if (st == WL_OK) st = S->layout(B, &L);
     }
@@ -955,7 +1051,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
             a.out_norm = fout[k].n;
             a.epi.coef = coef;
             a.red = no_red();
-            return launch_hop(prec, recon, false, cfg / 1024, a, B, s);
+            return launch_hop(prec, recon, false, false, cfg / 1024, a, B, s);
         };
         for (int k = 0; k < nsets && st == WL_OK; ++k)
             if (launch(k) != hipSuccess) st = set_error(WL_ERR_HIP, "hop launch failed");

@@ -379,7 +379,84 @@ struct SysDesc {
     int32_t gstride;     // chunk stride of the packed links (== stride)
     int32_t pad_;
     const void *gauge;   // packed links of the precision used by the launch
+    const void *clov;    // packed clover term A (null: Wilson system), [parity][chunk][stride]
+    const void *clovinv; // packed A^{-1}
 };
+
+// ------------------------------------------------------------------ clover term
+//
+// A(x) = 1 + i kappa c_sw sum_{m<n} s_mn F_mn(x) commutes with g5, so in the
+// DeGrand-Rossi basis it is two Hermitian 6x6 blocks: block b acts on spins
+// 2b, 2b+1 (all colours), i.e. on the 12 reals o[12b .. 12b+11].  A block is
+// packed as 36 reals: the 6 real diagonal entries, then the 15 entries above
+// the diagonal in row-major order as (re, im).  FP64 stores 36 double2 rows per
+// site, FP32 18 float4 rows (FP16/BF16 launches use the FP32 copy).
+template <int P> struct CloverFmt {
+    using chunk = float4;
+    static constexpr int nchunk = 18;
+};
+template <> struct CloverFmt<P_F64> {
+    using chunk = double2;
+    static constexpr int nchunk = 36;
+};
+
+// packed index of entry (i, j), i < j, of a 6x6 block
+WL_HD int clov_upper(int i, int j) { return 6 + 2 * (i * 6 - i * (i + 1) / 2 + (j - i - 1)); }
+
+// o <- A o (or A^{-1} o for the inverse field) at site cb; base is the parity's chunk 0
+template <int P, class T>
+WL_HD void clover_apply(const void *base, int stride, int cb, T o[24])
+{
+    using CF = CloverFmt<P>;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        T m[36];
+        if constexpr (P == P_F64) {
+#pragma unroll
+            for (int c = 0; c < 18; ++c) {
+                const double2 w = *row_elem<double2>(base, 18 * b + c, stride, cb);
+                m[2 * c] = (T)w.x;
+                m[2 * c + 1] = (T)w.y;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const float4 w = *row_elem<typename CF::chunk>(base, 9 * b + c, stride, cb);
+                m[4 * c] = (T)w.x;
+                m[4 * c + 1] = (T)w.y;
+                m[4 * c + 2] = (T)w.z;
+                m[4 * c + 3] = (T)w.w;
+            }
+        }
+        T xr[6], xi[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            xr[k] = o[12 * b + 2 * k];
+            xi[k] = o[12 * b + 2 * k + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            T yr = m[i] * xr[i], yi = m[i] * xi[i];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                if (j == i) continue;
+                // M_ij = (re, im) for i < j; M_ij = conj(M_ji) for i > j
+                const int u = i < j ? clov_upper(i, j) : clov_upper(j, i);
+                const T mr = m[u], mi = i < j ? m[u + 1] : -m[u + 1];
+                yr += mr * xr[j] - mi * xi[j];
+                yi += mr * xi[j] + mi * xr[j];
+            }
+            o[12 * b + 2 * i] = yr;
+            o[12 * b + 2 * i + 1] = yi;
+        }
+    }
+}
+
+// base of parity `par` of a packed clover field
+template <int P> WL_HD const void *clover_parity(const void *f, int par, int stride)
+{
+    return (const char *)f + (size_t)par * CloverFmt<P>::nchunk * stride * sizeof(typename CloverFmt<P>::chunk);
+}
 
 // site coordinates from checkerboard index and parity
 struct Site {
@@ -629,7 +706,7 @@ template <class T> WL_HD void sched_fence(T acc[24])
 
 // acc = (H psi)(x) (or H^dagger) at output site cb of `parity`; psi is read on
 // the other parity.  FENCE = number of directions whose operands may be in
-// flight together (1, 2 or 8); NT = non-temporal link loads.
+// flight together (1, 2, 4 or 8); NT = non-temporal link loads.
 template <int SP, int GP, int R, bool DAG, int FENCE = 2, bool NT = true, class T>
 WL_HD void hop_site(const SysDesc &d, const HopSite &a, int parity, int cb, T acc[24])
 {
@@ -643,7 +720,7 @@ WL_HD void hop_site(const SysDesc &d, const HopSite &a, int parity, int cb, T ac
     hop_dir<SP, GP, R, 1, +1, DAG, NT>(d, a, parity, s, cb, acc);
     if constexpr (FENCE == 1) WL_SCHED_FENCE();
     hop_dir<SP, GP, R, 1, -1, DAG, NT>(d, a, parity, s, cb, acc);
-    if constexpr (FENCE <= 2) WL_SCHED_FENCE();
+    if constexpr (FENCE <= 4) WL_SCHED_FENCE();
     hop_dir<SP, GP, R, 2, +1, DAG, NT>(d, a, parity, s, cb, acc);
     if constexpr (FENCE == 1) WL_SCHED_FENCE();
     hop_dir<SP, GP, R, 2, -1, DAG, NT>(d, a, parity, s, cb, acc);

@@ -54,12 +54,22 @@ struct wl_gauge_s {
     int device = 0;
     double *U = nullptr;       // canonical FP64 copy (device)
     void *packed[4][2] = {};   // [prec][recon == 12]
+    // clover term A and A^{-1} per value of kappa * c_sw, FP64 [0] and FP32 [1]
+    struct Clover {
+        double kc;
+        void *A[2];
+        void *Ainv[2];
+    };
+    std::vector<Clover> clovers;
     ~wl_gauge_s();
 };
 
 namespace wl {
 
 wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const void **out);
+// packed clover term A and A^{-1} for kappa * c_sw = kc in the storage a hop of
+// precision prec reads (FP64 for FP64, FP32 otherwise), built on first use
+wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const void **A, const void **Ainv);
 
 // ------------------------------------------------------------------ execution sets
 
@@ -81,6 +91,7 @@ struct SysEntry {
     wl_gauge g;
     int nrhs;
     double kappa;
+    double csw = 0.0;  // clover coefficient; 0: Wilson operator
 };
 
 // A set of systems (each a gauge handle with nrhs right-hand sides) whose
@@ -92,11 +103,12 @@ public:
     wl_status init();
 
     std::vector<SysEntry> systems;
+    bool has_clover = false;   // some system carries a clover term
     std::vector<VecDesc> vec;  // nblk / pslot0 filled per layout
     int nvec = 0;
     size_t total_sites = 0;    // sum of strides over vectors
 
-    // device tables
+    // device tables: prec < 0 geometry only; recon 0: no links (geometry and clover term)
     wl_status sys_table(int prec, int recon, hipStream_t s, const SysDesc **out);
     wl_status layout(int B, const Layout **out);
     int32_t *d_active = nullptr;
@@ -135,6 +147,7 @@ void drop_sets_of(wl_gauge g);
 struct Epi {
     int nx = 0;
     int g5 = 0;
+    int clov = 0;  // EPI_CLOV_* bits (act only on systems with a clover term)
     const double *coef = nullptr;  // device [nsys][5]
     Field X[4];
 };
@@ -146,7 +159,7 @@ RedSpec red_spec(ExecSet &S, int kind, double *dst, int nv = 1, int mode = RM_NO
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int out_parity, const Field &out, const Field &in,
               const Epi &e, const RedSpec &red, hipStream_t s, bool use_active = true);
 wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
-               hipStream_t s, bool use_active = true);
+               hipStream_t s, bool use_active = true, int parity = 0);
 wl_status convert(ExecSet &S, const Field &dst, const Field &src, hipStream_t s, bool use_active = true);
 // canonical <-> packed for one parity; canon[i] is the canonical field array of system i
 wl_status pack(ExecSet &S, const double *const *canon, int parity, const Field &f, hipStream_t s);
@@ -182,38 +195,37 @@ int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream
                 const std::function<hipError_t(int)> &run);
 bool capturing(hipStream_t s);
 std::string hop_key(const ExecSet &S, int prec, int recon, bool dag);
-std::vector<int> hop_candidates();
+std::vector<int> hop_candidates(int prec);
 
-// Event pairs around hop launches and the algorithmic GB of each launch
+// Kernel timing of hop launches (eager launches only: a solver runs without
+// graphs while timing is on).  Each timed launch carries start/end events that
+// its dispatch records, and its blocks store steady-clock readings at their
+// start and end, from which the kernel's own duration follows.
 struct EventList {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<double> gbytes;
 };
-
-// Kernel timing of hop launches.  Eager launches carry start/end events of
-// their own dispatch; launches captured into a graph get event-record nodes
-// around them, read after every replay of that graph (the CP has the next
-// packet in hand, so graph intervals carry almost no launch latency).
 struct Prof {
     bool on = false;
-    bool graphs_only = false;  // time only launches replayed from graphs
-    int prec = -1;             // storage precision of the hops timed (-1: all)
+    int prec = -1;  // storage precision of the hops timed (-1: all)
     int64_t launches = 0;
-    double ms = 0.0;
+    double ms = 0.0;         // dispatch events
+    double kernel_ms = 0.0;  // device steady clock: first block start to last block end
     double gbytes = 0.0;
-    EventList pending;                        // eager launches, read once
-    EventList *capture = nullptr;             // graph being captured: its hop events
-    std::map<const void *, EventList> graph;  // per instantiated graph
-    const EventList *replayed = nullptr;      // events of the last replayed graph
+    EventList pending;
+    unsigned long long *d_stamps = nullptr;  // device block stamps of one launch
+    std::vector<unsigned long long> h_stamps;
+    size_t nstamps = 0;
+    double clock_khz = 0.0;
 };
 Prof &prof();
 void prof_collect();
-// accumulate the events of the last replayed graph (its stream must be synchronised)
-void prof_collect_graph();
 
 // algorithmic bytes of one hop on all active vectors of the set
 double hop_bytes(const ExecSet &S, int prec, int recon, bool use_active);
 double blas_bytes(const ExecSet &S, int prec, int passes, bool use_active);
+// algorithmic bytes of reading one packed clover field at every output site of the clover systems
+double clover_bytes(const ExecSet &S, int prec, bool use_active);
 extern thread_local double g_bytes_acc;  // running algorithmic-byte counter of the current call
 
 }  // namespace wl

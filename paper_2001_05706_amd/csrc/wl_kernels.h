@@ -11,7 +11,7 @@ struct BlasArgs {
     const BlkMap *map;
     const int32_t *active;
     int32_t nblocks;
-    int32_t pad_;
+    int32_t parity;    // parity of the fields (clover operations)
     void *f[6];
     float *fn[6];
     const double *s0;  // per-vector scalar (alpha or beta)
@@ -35,11 +35,12 @@ struct PackArgs {
 };
 
 // hop.hip
-// var selects a launch variant (0 .. hop_variants()-1, see hop.hip); with
-// events e0/e1 the dispatch records them at the kernel's start and end
-hipError_t launch_hop(int prec, int recon, bool dag, int var, const HopArgs &a, int block, hipStream_t s,
+// var selects a launch variant (0 .. hop_variants(prec)-1, see hop.hip); clov
+// selects the instantiation with the clover epilogue; with events e0/e1 the
+// dispatch records them at the kernel's start and end
+hipError_t launch_hop(int prec, int recon, bool dag, bool clov, int var, const HopArgs &a, int block, hipStream_t s,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-int hop_variants();
+int hop_variants(int prec);  // launch variants available for a storage precision
 
 // blas.hip -- all operate on the vectors of one set through its block map
 enum BlasOp {
@@ -57,6 +58,7 @@ enum BlasOp {
     BL_BICG_XR = 10,   // x += alpha p + omega s; r = s - omega t; <rhat, r>, |r|^2         f = {x, p, s, r, t, rhat}
     BL_CDOT = 11,      // <a, b>                                                            f = {a, b}
     BL_G5COPY = 12,    // y = g5 x                                                          f = {y, x}
+    BL_CLOV_INV = 13,  // y = A^{-1} x on parity `parity` (clover systems; a copy otherwise)  f = {y, x}
 };
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
 // fixed-order sum of each active vector's block partials and the reduction's finishing step
@@ -70,6 +72,12 @@ hipError_t launch_unpack_spinor(int prec, const PackArgs &a, int block, hipStrea
 hipError_t launch_zero_canon(const PackArgs &a, int block, hipStream_t s);
 hipError_t launch_pack_gauge(int prec, int recon, const double *U_canon, void *out, const SysDesc &d,
                              hipStream_t s);
+
+// clover.hip: A = 1 + i kc sum_{m<n} s_mn F_mn from the canonical links, packed
+// FP64 and FP32; then A^{-1} from the FP64 A
+hipError_t launch_clover_build(const double *U_canon, const SysDesc &d, double kc, void *A64, void *A32,
+                               hipStream_t s);
+hipError_t launch_clover_invert(const SysDesc &d, const void *A64, void *Ainv64, void *Ainv32, hipStream_t s);
 hipError_t launch_copy_bw(const void *in, void *out, size_t bytes, hipStream_t s);
 
 }  // namespace wl

@@ -84,12 +84,17 @@ struct RedSpec {
 };
 
 // Linear combination applied to the hopping term at the output site:
-//   out = G5?( a0 X0 + c hop ) + a1 X1 + a2 X2 + a3 X3
+//   out = Ci G5?( a0 C0 X0 + c hop ) + a1 X1 + a2 X2 + a3 X3
 // with coefficients per system in device memory: coef[sys * 5 + {0..3: a0..a3, 4: c}].
-// The X fields share the output's precision and parity.
+// The X fields share the output's precision and parity.  For a system with a
+// clover term, C0 = A (clov bit 0) and Ci = A^{-1} (clov bit 1) at the output
+// site; otherwise both are 1.
+enum { EPI_CLOV_X0 = 1, EPI_CLOV_INV = 2 };
 struct EpiSpec {
     int32_t nx;          // number of X fields used (0..4)
     int32_t g5;          // apply gamma_5 to (a0 X0 + c hop)
+    int32_t clov;        // EPI_CLOV_* bits
+    int32_t pad_;
     const double *coef;
     const void *X[4];
     const float *Xn[4];  // norms for FP16/BF16
@@ -109,6 +114,9 @@ struct HopArgs {
     float *out_norm;
     EpiSpec epi;
     RedSpec red;
+    // kernel timing (null: off): each block stores its first and last steady-clock
+    // reading at stamps[2 * logical block + {0, 1}]
+    unsigned long long *stamps;
 };
 
 }  // namespace wl

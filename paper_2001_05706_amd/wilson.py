@@ -62,6 +62,10 @@ SIGNATURES = [
     ("wilson_cg_multi", _i32, [_i32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                ctypes.POINTER(_i32), ctypes.POINTER(_d), _d, _i32, _i32, _i32, _d,
                                ctypes.POINTER(WlSolveInfo), _P]),
+    ("wilson_clover_dslash", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _i32, _i32, _P]),
+    ("wilson_clover_cg", _i32, [_P, _P, _P, _i32, _d, _d, _d, _i32, _i32, _i32, _d, ctypes.POINTER(WlSolveInfo), _P]),
+    ("wilson_clover_bicgstab", _i32, [_P, _P, _P, _i32, _d, _d, _d, _i32, _i32, _i32, _d,
+                                      ctypes.POINTER(WlSolveInfo), _P]),
     ("overlap_sign_cheb", _i32, [_P, _P, _P, _i32, _d, _i32, _d, _d, _d, _i32, _i32, _P]),
     ("overlap_dslash", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _i32, _i32, _i32, _P]),
     ("overlap_cg", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _d, _i32, _i32, _i32, _d,
@@ -73,7 +77,7 @@ SIGNATURES = [
     ("wl_bench_copy", _i32, [_i64, _i32, ctypes.POINTER(_d), _P]),
     ("wl_prof_enable", _i32, [_i32]),
     ("wl_prof_select", _i32, [_i32]),
-    ("wl_prof_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    ("wl_prof_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     ("wl_hop_bytes_per_site", _d, [_i32, _i32, _i32]),
 ]
 
@@ -211,6 +215,33 @@ def wilson_cg_multi(Us, etas, xs, nrhs, kappas, tol, maxiter, sloppy="f32", reco
     return st, res
 
 
+def wilson_clover_dslash(U: Gauge, inp, out, nrhs, kappa, csw, dagger=0, prec="f32", recon=12, stream=None):
+    return _check(lib().wilson_clover_dslash(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(kappa),
+                                             float(csw), int(dagger), _prec(prec), int(recon), _stream(stream)))
+
+
+def _clover_solve(fn, U, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy, recon, delta, stream, check):
+    infos = (WlSolveInfo * int(nrhs))()
+    st = fn(U.handle, _ptr(eta, "eta"), _ptr(x, "x"), int(nrhs), float(kappa), float(csw), float(tol), int(maxiter),
+            _prec(sloppy), int(recon), float(delta), infos, _stream(stream))
+    res = [i.as_dict() for i in infos]
+    if check:
+        _check(st, res)
+    return st, res
+
+
+def wilson_clover_cg(U: Gauge, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy="f32", recon=12, delta=0.1,
+                     stream=None, check=True):
+    return _clover_solve(lib().wilson_clover_cg, U, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy, recon, delta,
+                         stream, check)
+
+
+def wilson_clover_bicgstab(U: Gauge, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy="f32", recon=12, delta=0.1,
+                           stream=None, check=True):
+    return _clover_solve(lib().wilson_clover_bicgstab, U, eta, x, nrhs, kappa, csw, tol, maxiter, sloppy, recon,
+                         delta, stream, check)
+
+
 def overlap_sign_cheb(U: Gauge, inp, out, nrhs, rho, degree, lo, hi, scale, prec="f32", recon=12, stream=None):
     return _check(lib().overlap_sign_cheb(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(rho),
                                           int(degree), float(lo), float(hi), float(scale), _prec(prec), int(recon),
@@ -255,9 +286,8 @@ def wl_bench_copy(nbytes, reps=20, stream=None) -> float:
     return r.value
 
 
-def wl_prof_enable(on=1):
-    """0: off; 1: time every hop launch; 2: only hops replayed from captured graphs."""
-    _check(lib().wl_prof_enable(int(on)))
+def wl_prof_enable(on=True):
+    _check(lib().wl_prof_enable(int(bool(on))))
 
 
 def wl_prof_select(prec=-1):
@@ -265,11 +295,13 @@ def wl_prof_select(prec=-1):
 
 
 def wl_prof_read():
+    """(launches, event ms, algorithmic GB, kernel ms) of the timed hop launches since the last read."""
     n = ctypes.c_int64()
     ms = ctypes.c_double()
     gb = ctypes.c_double()
-    _check(lib().wl_prof_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(gb)))
-    return n.value, ms.value, gb.value
+    kms = ctypes.c_double()
+    _check(lib().wl_prof_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(gb), ctypes.byref(kms)))
+    return n.value, ms.value, gb.value, kms.value
 
 
 def wl_hop_bytes_per_site(prec="f32", recon=12, nrhs=1) -> float:

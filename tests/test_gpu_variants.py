@@ -21,7 +21,7 @@ def force(monkeypatch):
     return set_cfg
 
 
-@pytest.mark.parametrize("var", [0, 1, 2, 3])
+@pytest.mark.parametrize("var", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("block", [64, 512])
 def test_every_hop_variant_matches_oracle(var, block, force):
     w = need_gpu()
@@ -35,7 +35,7 @@ def test_every_hop_variant_matches_oracle(var, block, force):
             check(prec, got, expected(L, U, psi, 0.13, parity, dagger, prec, recon))
 
 
-@pytest.mark.parametrize("var", [0, 1, 2, 3])
+@pytest.mark.parametrize("var", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("sloppy", ["f16", "bf16"])
 def test_every_hop_variant_solves(var, sloppy, force):
     w = need_gpu()
