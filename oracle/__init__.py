@@ -75,8 +75,9 @@ def _load():
         lib.or_sign_cheb.argtypes = [P, i32, P, P, P, i32, d, i32, d, d, d]
         lib.or_hw2_lmax.argtypes = [P, i32, P, d, P, i32]
         lib.or_hw2_lmax.restype = d
-        lib.or_overlap.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, i32]
-        lib.or_overlap_cg.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, d, i32, P, P]
+        lib.or_sign_cheb_defl.argtypes = [P, i32, P, P, P, i32, d, i32, d, d, d, i32, P, P]
+        lib.or_overlap.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, i32, i32, P, P]
+        lib.or_overlap_cg.argtypes = [P, i32, P, P, P, i32, d, d, i32, d, d, d, d, i32, i32, P, P, P, P]
         lib.or_overlap_cg.restype = i32
         lib.or_clover.argtypes = [P, P, d, d, P]
         lib.or_wilson_clover.argtypes = [P, i32, P, P, P, i32, d, d, i32]
@@ -213,22 +214,53 @@ def hw2_lmax(L, U, rho: float, v0, iters: int = 200, antiperiodic_t: bool = True
     return float(_load().or_hw2_lmax(_p(L), int(antiperiodic_t), _p(U), float(rho), _p(a), int(iters)))
 
 
-def overlap(L, U, psi, rho: float, mass: float, degree: int, lo: float, hi: float, scale: float,
-            dagger: bool = False, antiperiodic_t: bool = True):
-    """D_ov(m) psi = (rho + m/2) psi + (rho - m/2) g5 eps(H_W) psi (dagger: eps g5)."""
+def _deflation(evecs, evals, V):
+    """(nev, evecs array, evals array) for the C calls; nev = 0 without deflation."""
+    if evecs is None:
+        return 0, None, None
+    ev = _field(evecs, V)
+    lam = np.ascontiguousarray(evals, dtype=np.float64)
+    if lam.shape != (ev.shape[0],):
+        raise ValueError("one eigenvalue per eigenvector")
+    return ev.shape[0], ev, lam
+
+
+def sign_cheb_defl(L, U, psi, rho: float, degree: int, lo: float, hi: float, scale: float, evecs, evals,
+                   antiperiodic_t: bool = True):
+    """eps(H_W) psi with the eigenpairs (evecs, evals) of H_W treated exactly and
+    the Chebyshev polynomial on their orthogonal complement."""
     L = _dims(L)
     V = int(np.prod(L))
     U = _links(U, V)
     a = _field(psi, V)
+    nev, ev, lam = _deflation(evecs, evals, V)
+    out = np.empty_like(a)
+    _load().or_sign_cheb_defl(_p(L), int(antiperiodic_t), _p(U), _p(a), _p(out), a.shape[0], float(rho), int(degree),
+                              float(lo), float(hi), float(scale), nev, _p(ev) if nev else None,
+                              _p(lam) if nev else None)
+    return out.reshape(np.shape(psi))
+
+
+def overlap(L, U, psi, rho: float, mass: float, degree: int, lo: float, hi: float, scale: float,
+            dagger: bool = False, antiperiodic_t: bool = True, evecs=None, evals=None):
+    """D_ov(m) psi = (rho + m/2) psi + (rho - m/2) g5 eps(H_W) psi (dagger: eps g5);
+    with (evecs, evals) the sign function is deflated by those eigenpairs of H_W."""
+    L = _dims(L)
+    V = int(np.prod(L))
+    U = _links(U, V)
+    a = _field(psi, V)
+    nev, ev, lam = _deflation(evecs, evals, V)
     out = np.empty_like(a)
     _load().or_overlap(_p(L), int(antiperiodic_t), _p(U), _p(a), _p(out), a.shape[0], float(rho), float(mass),
-                       int(degree), float(lo), float(hi), float(scale), int(dagger))
+                       int(degree), float(lo), float(hi), float(scale), int(dagger), nev, _p(ev) if nev else None,
+                       _p(lam) if nev else None)
     return out.reshape(np.shape(psi))
 
 
 def overlap_cg(L, U, eta, rho: float, mass: float, degree: int, lo: float, hi: float, scale: float, tol: float,
-               maxiter: int = 10000, x0=None, antiperiodic_t: bool = True):
-    """Solve D_ov(m) psi = eta by CGNR with the Chebyshev sign function.
+               maxiter: int = 10000, x0=None, antiperiodic_t: bool = True, evecs=None, evals=None):
+    """Solve D_ov(m) psi = eta by CGNR with the Chebyshev sign function (deflated
+    by (evecs, evals) when given).
 
     Returns (psi, converged, iters[nrhs], resid[nrhs]), resid = |eta - D_ov psi| / |eta|.
     """
@@ -238,11 +270,12 @@ def overlap_cg(L, U, eta, rho: float, mass: float, degree: int, lo: float, hi: f
     e = _field(eta, V)
     x = np.zeros_like(e) if x0 is None else _field(x0, V).copy()
     nrhs = e.shape[0]
+    nev, ev, lam = _deflation(evecs, evals, V)
     iters = np.zeros(nrhs, dtype=np.int32)
     res = np.zeros(nrhs, dtype=np.float64)
     st = _load().or_overlap_cg(_p(L), int(antiperiodic_t), _p(U), _p(e), _p(x), nrhs, float(rho), float(mass),
-                               int(degree), float(lo), float(hi), float(scale), float(tol), int(maxiter),
-                               _p(iters), _p(res))
+                               int(degree), float(lo), float(hi), float(scale), float(tol), int(maxiter), nev,
+                               _p(ev) if nev else None, _p(lam) if nev else None, _p(iters), _p(res))
     return x.reshape(np.shape(eta)), st == 0, iters, res
 
 

@@ -471,6 +471,45 @@ void or_sign_cheb(const int32_t *L, int32_t antiperiodic_t, const double *U, con
     free(c); free(b0); free(b1); free(b2); free(w); free(yb);
 }
 
+/* ---- low-mode deflation of the sign function ----------------------------- */
+/* With nev orthonormal eigenvectors xi_i of H_W (eigenvalues lambda_i) the
+ * sign function acts exactly on their span and by the polynomial on the rest:
+ *   eps(H_W) v = sum_i sign(lambda_i) xi_i <xi_i, v> + eps_poly(H_W) (v - sum_i xi_i <xi_i, v>)
+ * evecs: nev whole-lattice fields; nev = 0 is the plain polynomial. */
+static void sign_deflated(const int32_t *L, int32_t antiperiodic_t, const double *U, const cplx *v, cplx *out,
+                          double rho, int32_t degree, double lo, double hi, double scale, int32_t nev,
+                          const double *evecs_, const double *evals)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    if (nev <= 0) {
+        or_sign_cheb(L, antiperiodic_t, U, (const double *)v, (double *)out, 1, rho, degree, lo, hi, scale);
+        return;
+    }
+    const cplx *xi = (const cplx *)evecs_;
+    cplx *w = malloc(sizeof(cplx) * n), *c = malloc(sizeof(cplx) * nev);
+    memcpy(w, v, sizeof(cplx) * n);
+    for (int i = 0; i < nev; ++i) {
+        c[i] = vdot(xi + (size_t)i * n, v, n);
+        vaxpby(-c[i], xi + (size_t)i * n, 1.0, w, n);
+    }
+    or_sign_cheb(L, antiperiodic_t, U, (const double *)w, (double *)out, 1, rho, degree, lo, hi, scale);
+    for (int i = 0; i < nev; ++i) vaxpby((evals[i] > 0 ? 1.0 : -1.0) * c[i], xi + (size_t)i * n, 1.0, out, n);
+    free(w); free(c);
+}
+
+/* the deflated sign function on nrhs fields */
+void or_sign_cheb_defl(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
+                       double *out_, int32_t nrhs, double rho, int32_t degree, double lo, double hi,
+                       double scale, int32_t nev, const double *evecs, const double *evals)
+{
+    lattice g = make_lattice(L, antiperiodic_t);
+    long n = g.V * 12;
+    for (int r = 0; r < nrhs; ++r)
+        sign_deflated(L, antiperiodic_t, U, (const cplx *)in_ + (size_t)r * n, (cplx *)out_ + (size_t)r * n, rho,
+                      degree, lo, hi, scale, nev, evecs, evals);
+}
+
 /* ---- overlap operator (GWU-code's inverter, Sections 1 and 3) ----------- */
 /* Neuberger's overlap operator with bare mass m, built on the approximate
  * sign function above:
@@ -479,7 +518,8 @@ void or_sign_cheb(const int32_t *L, int32_t antiperiodic_t, const double *U, con
  * whole lattice, nrhs fields. */
 void or_overlap(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *in_,
                 double *out_, int32_t nrhs, double rho, double mass, int32_t degree, double lo,
-                double hi, double scale, int32_t dagger)
+                double hi, double scale, int32_t dagger, int32_t nev, const double *evecs,
+                const double *evals)
 {
     lattice g = make_lattice(L, antiperiodic_t);
     long n = g.V * 12;
@@ -490,9 +530,9 @@ void or_overlap(const int32_t *L, int32_t antiperiodic_t, const double *U, const
         cplx *out = (cplx *)out_ + (size_t)r * n;
         if (dagger) {
             vgamma5(v, t, g.V);
-            or_sign_cheb(L, antiperiodic_t, U, (const double *)t, (double *)w, 1, rho, degree, lo, hi, scale);
+            sign_deflated(L, antiperiodic_t, U, t, w, rho, degree, lo, hi, scale, nev, evecs, evals);
         } else {
-            or_sign_cheb(L, antiperiodic_t, U, (const double *)v, (double *)t, 1, rho, degree, lo, hi, scale);
+            sign_deflated(L, antiperiodic_t, U, v, t, rho, degree, lo, hi, scale, nev, evecs, evals);
             vgamma5(t, w, g.V);
         }
 #pragma omp parallel for schedule(static)
@@ -511,8 +551,8 @@ void or_overlap(const int32_t *L, int32_t antiperiodic_t, const double *U, const
  * resid_out: |eta - D x| / |eta| with the same operator, recomputed. */
 int32_t or_overlap_cg(const int32_t *L, int32_t antiperiodic_t, const double *U, const double *eta_,
                       double *x_, int32_t nrhs, double rho, double mass, int32_t degree, double lo,
-                      double hi, double scale, double tol, int32_t maxiter, int32_t *iters_out,
-                      double *resid_out)
+                      double hi, double scale, double tol, int32_t maxiter, int32_t nev,
+                      const double *evecs, const double *evals, int32_t *iters_out, double *resid_out)
 {
     lattice g = make_lattice(L, antiperiodic_t);
     long n = g.V * 12;
@@ -520,7 +560,8 @@ int32_t or_overlap_cg(const int32_t *L, int32_t antiperiodic_t, const double *U,
     cplx *p = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
     int32_t status = 0;
 #define OV_APPLY(in, out, dag) \
-    or_overlap(L, antiperiodic_t, U, (const double *)(in), (double *)(out), 1, rho, mass, degree, lo, hi, scale, dag)
+    or_overlap(L, antiperiodic_t, U, (const double *)(in), (double *)(out), 1, rho, mass, degree, lo, hi, scale, dag, \
+               nev, evecs, evals)
     for (int rh = 0; rh < nrhs; ++rh) {
         const cplx *eta = (const cplx *)eta_ + (size_t)rh * n;
         cplx *x = (cplx *)x_ + (size_t)rh * n;

@@ -55,8 +55,10 @@ MUTATIONS = [
     ("overlap mass enters both terms with one sign", "b = rho - 0.5 * mass;", "b = rho + 0.5 * mass;"),
     ("overlap missing gamma5", "            vgamma5(t, w, g.V);\n", "            memcpy(w, t, sizeof(cplx) * n);\n"),
     ("overlap adjoint equals the operator",
-     "            vgamma5(v, t, g.V);\n            or_sign_cheb(L, antiperiodic_t, U, (const double *)t, (double *)w,",
-     "            vgamma5(v, t, g.V);\n            or_sign_cheb(L, antiperiodic_t, U, (const double *)v, (double *)w,"),
+     "            vgamma5(v, t, g.V);\n            sign_deflated(L, antiperiodic_t, U, t, w,",
+     "            vgamma5(v, t, g.V);\n            sign_deflated(L, antiperiodic_t, U, v, w,"),
+    ("deflated modes keep the polynomial sign", "(evals[i] > 0 ? 1.0 : -1.0) * c[i]", "0.0 * c[i]"),
+    ("deflated modes not projected out", "        vaxpby(-c[i], xi + (size_t)i * n, 1.0, w, n);\n", "\n"),
     ("overlap CG residual update sign", "            vaxpby(-alpha, q, 1.0, rt, n);\n            OV_APPLY",
      "            vaxpby(alpha, q, 1.0, rt, n);\n            OV_APPLY"),
     ("clover leaf link not daggered", "const int d1[4] = {0, 0, 1, 1};", "const int d1[4] = {0, 0, 0, 1};"),
@@ -130,6 +132,7 @@ def battery(cases):
     yield lambda: ovpins.test_overlap_matches_dense_exact_sign(cases["ov"], 0.25)
     yield lambda: ovpins.test_overlap_ginsparg_wilson_and_normality(cases["ov"])
     yield lambda: ovpins.test_overlap_cg_matches_dense_solve(cases["ov"])
+    yield lambda: ovpins.test_deflated_sign_is_exact_outside_the_window(cases["ov"])
     yield lambda: clpins.test_abelian_flux_closed_form(1, 2)
     yield lambda: clpins.test_clover_hermitian_chiral_blocks(cases["clover"])
     yield lambda: clpins.test_clover_gamma5_hermiticity_and_gauge_covariance(cases["clover"])

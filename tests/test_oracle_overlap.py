@@ -9,7 +9,10 @@ sign function are fixed by the mathematics, not by the oracle:
   * Ginsparg-Wilson relation at m = 0: g5 D + D g5 = D g5 D / rho;
   * g5 eps is unitary, so D(0)/rho - 1 preserves norms, and D is normal;
   * D(m) = (1 - m / (2 rho)) D(0) + m;
-  * the CG solution matches a LAPACK solve of the dense exact operator.
+  * the CG solution matches a LAPACK solve of the dense exact operator;
+  * deflation: with the lowest eigenvectors of H_W treated exactly, a window
+    that leaves them out still gives the exact sign function, while the
+    undeflated polynomial on that window does not.
 """
 import numpy as np
 import pytest
@@ -47,7 +50,7 @@ def make_case():
     lo = 0.9 * lam2.min() / scale
     S = (vec * np.sign(w)) @ vec.conj().T
     G5 = dw.gamma5_matrix(V)
-    return {"L": L, "U": U, "V": V, "scale": scale, "lo": lo, "S": S, "G5": G5}
+    return {"L": L, "U": U, "V": V, "scale": scale, "lo": lo, "S": S, "G5": G5, "w": w, "vec": vec}
 
 
 @pytest.fixture(scope="module")
@@ -126,3 +129,40 @@ def test_overlap_cg_zero_source_and_guess(ov):
     x2, conv2, iters2, res2 = oracle.overlap_cg(ov["L"], ov["U"], eta, RHO, mass, DEG, ov["lo"], 1.0, ov["scale"],
                                                tol=1e-10, x0=x)
     assert conv and conv2 and iters2[0] == 0 and res2[0] <= 1e-10
+
+
+def low_modes(ov, nev):
+    """The nev eigenpairs of the dense H_W of smallest |lambda|, as canonical fields."""
+    order = np.argsort(np.abs(ov["w"]))[:nev]
+    vecs = ov["vec"][:, order].T.reshape(nev, ov["V"], 4, 3)
+    return vecs, ov["w"][order], np.abs(ov["w"][np.argsort(np.abs(ov["w"]))[nev]])
+
+
+def test_deflated_sign_is_exact_outside_the_window(ov):
+    nev = 32
+    vecs, lam, next_abs = low_modes(ov, nev)
+    lo = 0.9 * next_abs ** 2 / ov["scale"]  # the window leaves out the deflated modes
+    assert lo > 1.2 * ov["lo"]
+    psi = li.gaussian_spinor(ov["L"], 2107, nrhs=2)
+    got = oracle.sign_cheb_defl(ov["L"], ov["U"], psi, RHO, DEG, lo, 1.0, ov["scale"], vecs, lam)
+    for r in range(2):
+        assert rel(got[r], ov["S"] @ psi[r].ravel()) < 1e-9
+    # without the deflation the same window misses the low modes
+    plain = oracle.sign_cheb(ov["L"], ov["U"], psi, RHO, DEG, lo, 1.0, ov["scale"])
+    assert rel(plain[0], ov["S"] @ psi[0].ravel()) > 1e-6
+    # the deflated overlap operator satisfies Ginsparg-Wilson on that window too
+    D0 = lambda v: oracle.overlap(ov["L"], ov["U"], v, RHO, 0.0, DEG, lo, 1.0, ov["scale"], evecs=vecs, evals=lam)
+    lhs = g5(D0(psi[0])) + D0(g5(psi[0]))
+    assert rel(lhs, D0(g5(D0(psi[0]))) / RHO) < 1e-9
+
+
+def test_deflated_overlap_cg_matches_dense_solve(ov):
+    nev = 32
+    vecs, lam, next_abs = low_modes(ov, nev)
+    lo = 0.9 * next_abs ** 2 / ov["scale"]
+    mass = 0.2
+    eta = li.gaussian_spinor(ov["L"], 2108)
+    x, conv, iters, res = oracle.overlap_cg(ov["L"], ov["U"], eta, RHO, mass, DEG, lo, 1.0, ov["scale"], tol=1e-11,
+                                            maxiter=150, evecs=vecs, evals=lam)
+    assert conv and res[0] <= 1e-11
+    assert rel(x, np.linalg.solve(dense_overlap(ov, mass), eta.ravel())) < 1e-8
