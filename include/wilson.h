@@ -191,7 +191,32 @@ wl_status wilson_clover_bicgstab(wl_gauge U, const double *eta, double *x, int32
  * precision of the iteration (WL_F64 or WL_F32).  Synchronises `stream`. */
 wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t nrhs, double rho,
                             int32_t degree, double lo, double hi, double scale, wl_prec prec,
-                            int32_t recon, void *stream);
+                            int32_t recon, int32_t nev, const double *evecs, const double *evals,
+                            void *stream);
+
+/* Low-mode deflation (the last three arguments of overlap_sign_cheb,
+ * overlap_dslash and overlap_cg): nev in [0, 64] orthonormal eigenvectors of
+ * H_W (evecs: device, nev canonical whole-lattice fields) with their
+ * eigenvalues (evals: host, nev doubles).  The sign function then acts exactly
+ * on their span and by the polynomial on its orthogonal complement:
+ *   eps(H_W) v = sum_i sign(lambda_i) xi_i <xi_i, v> + eps_poly(H_W) (v - sum_i xi_i <xi_i, v>),
+ * so the window [lo, hi] only has to cover the rest of the spectrum.  nev = 0
+ * (evecs, evals may be NULL) is the plain polynomial.  wl_hw_eigs computes
+ * such eigenpairs. */
+
+/* The nev eigenpairs of H_W (m0 = -rho) of smallest |lambda|, by
+ * Chebyshev-filtered subspace iteration on H_W^2 in FP64 with a block of
+ * nblock vectors (nev <= nblock <= 64): each pass applies T_degree of H_W^2
+ * mapped so that the window [a, 1] of H_W^2 / scale is damped (a = the
+ * block's largest Ritz value, 0.05 at first), orthonormalises the block and
+ * takes Ritz pairs of H_W.  scale <= 0: 1.02 x a power-iteration estimate of
+ * lambda_max(H_W^2).  Stops when every wanted residual |H_W xi - lambda xi|
+ * <= tol or after maxiter passes (WL_ERR_NOCONV, results filled).  evecs:
+ * device, nev canonical fields (orthonormal, ordered by |lambda|); evals,
+ * resid: host, nev doubles; iters: host (may be NULL).  Synchronises. */
+wl_status wl_hw_eigs(wl_gauge U, double rho, int32_t nev, int32_t nblock, int32_t degree, double tol,
+                     int32_t maxiter, double scale, double *evecs, double *evals, double *resid, int32_t *iters,
+                     void *stream);
 
 /* ---------------------------------------------------------------- overlap operator */
 
@@ -206,7 +231,7 @@ wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t n
  * Synchronises `stream`. */
 wl_status overlap_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double rho, double mass,
                          int32_t degree, double lo, double hi, double scale, int32_t dagger, wl_prec prec,
-                         int32_t recon, void *stream);
+                         int32_t recon, int32_t nev, const double *evecs, const double *evals, void *stream);
 
 /* Solve D_ov(m) x = eta for nrhs canonical fields (device; x holds the initial
  * guess on entry and the solution on exit; eta and x must not overlap).  CG on
@@ -224,7 +249,8 @@ wl_status overlap_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs
  * Synchronises `stream`. */
 wl_status overlap_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double rho, double mass,
                      int32_t degree, double lo, double hi, double scale, double tol, int32_t maxiter,
-                     wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info, void *stream);
+                     wl_prec sloppy, int32_t recon, double delta, int32_t nev, const double *evecs,
+                     const double *evals, wl_solve_info *info, void *stream);
 
 /* Largest eigenvalue of H_W^2 (m0 = -rho) estimated by `iters` steps of power
  * iteration from the canonical field v0 (device); FP64.  Synchronises. */

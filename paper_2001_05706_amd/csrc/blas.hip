@@ -30,6 +30,12 @@ template <int P> __device__ __forceinline__ void *vbase(void *f, const VecDesc &
 }
 __device__ __forceinline__ float *nbase(float *n, const VecDesc &vd) { return n ? n + vd.site_off : nullptr; }
 
+// field j of the launch for vector vd: a shared single vector when its bcast bit is set
+template <int P> __device__ __forceinline__ const void *fbase(const BlasArgs &a, int j, const VecDesc &vd)
+{
+    return (a.bcast >> j) & 1 ? a.f[j] : vbase<P>(a.f[j], vd);
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
 {
@@ -252,11 +258,58 @@ __global__ __launch_bounds__(256) void k_cdot(BlasArgs a)
     double rv[3] = {0.0, 0.0, 0.0};
     if (live) {
         T x[24], y[24];
-        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P>(fbase<P>(a, 0, vd), nbase(a.fn[0], vd), sd.stride, cb, x);
         load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, y);
         site_cdot(x, y, rv[0], rv[1]);
     }
     block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+}
+
+// y += z x (G5: y += z g5 x) with the complex z of this vector from s0
+template <int P, bool G5>
+__global__ __launch_bounds__(256) void k_caxpy(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    const T zr = (T)a.s0[2 * bm.v], zi = (T)a.s0[2 * bm.v + 1];
+    T x[24], y[24];
+    load_spinor<P>(fbase<P>(a, 1, vd), nbase(a.fn[1], vd), sd.stride, cb, x);
+    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, y);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const T s = (G5 && k >= 6) ? (T)-1 : (T)1;
+        y[2 * k] += s * (zr * x[2 * k] - zi * x[2 * k + 1]);
+        y[2 * k + 1] += s * (zr * x[2 * k + 1] + zi * x[2 * k]);
+    }
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, y);
+}
+
+// y_v = sum_j T[j + nvec v] x_j over the vectors j of a single-system set
+// (vector j starts j strides into the field); T complex in s0
+template <int P>
+__global__ __launch_bounds__(256) void k_rot(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    using CH = typename SpinorFmt<P>::chunk;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    T y[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) y[k] = 0;
+    for (int j = 0; j < a.nvec; ++j) {
+        const double *t = a.s0 + 2 * ((size_t)j + (size_t)a.nvec * bm.v);
+        const T tr = (T)t[0], ti = (T)t[1];
+        T x[24];
+        load_spinor<P>((const CH *)a.f[1] + (size_t)j * sd.stride * SpinorFmt<P>::nchunk,
+                       a.fn[1] ? a.fn[1] + (size_t)j * sd.stride : nullptr, sd.stride, cb, x);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            y[2 * k] += tr * x[2 * k] - ti * x[2 * k + 1];
+            y[2 * k + 1] += tr * x[2 * k + 1] + ti * x[2 * k];
+        }
+    }
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, y);
 }
 
 // y = g5 x: spins 2 and 3 (the last 12 reals of a site) change sign
@@ -322,6 +375,9 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
     case BL_CDOT: hipLaunchKernelGGL(k_cdot<P>, g, b, 0, s, a); break;
     case BL_G5COPY: hipLaunchKernelGGL(k_g5copy<P>, g, b, 0, s, a); break;
     case BL_CLOV_INV: hipLaunchKernelGGL(k_clov_inv<P>, g, b, 0, s, a); break;
+    case BL_CAXPY: hipLaunchKernelGGL((k_caxpy<P, false>), g, b, 0, s, a); break;
+    case BL_CAXPY_G5: hipLaunchKernelGGL((k_caxpy<P, true>), g, b, 0, s, a); break;
+    case BL_ROT: hipLaunchKernelGGL(k_rot<P>, g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

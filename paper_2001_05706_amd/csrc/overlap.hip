@@ -34,6 +34,7 @@ struct Overlap {
     SignPlan P;
     int recon = 12;
     double a = 0, b = 0;  // rho + m/2, rho - m/2
+    Deflation D;          // low modes of H_W treated exactly (nev = 0: none)
 };
 
 // out = alpha D v + beta1 X1 + beta2 X2 (dagger: D^dagger), both parities.
@@ -44,13 +45,20 @@ wl_status ov_apply(Overlap &O, int prec, bool dagger, const Field out[2], const 
 {
     ExecSet &S = *O.S;
     Field in[2] = {v[0], v[1]};
-    if (dagger) {
-        // eps acts on g5 v
+    if (dagger || O.D.nev) {
+        // eps acts on g5 v (adjoint) or on a copy that the deflation projects
         for (int p = 0; p < 2; ++p) {
             WL_TRY(S.field("ov_g5v" + std::to_string(p), prec, &in[p]));
             const Field f[2] = {in[p], v[p]};
-            WL_TRY(blas(S, BL_G5COPY, prec, f, 2, nullptr, no_red(), s));
+            WL_TRY(blas(S, dagger ? BL_G5COPY : BL_COPY, prec, f, 2, nullptr, no_red(), s));
         }
+    }
+    std::vector<std::complex<double>> c, z;
+    if (O.D.nev) {
+        WL_TRY(defl_coeffs(S, O.D, prec, in, c, s));
+        z.resize(c.size());
+        for (size_t k = 0; k < c.size(); ++k) z[k] = -c[k];
+        WL_TRY(defl_axpy(S, O.D, prec, in, z, false, s));
     }
     Field y[2];
     WL_TRY(sign_poly(S, prec, O.recon, O.P, in, y, s));
@@ -69,8 +77,18 @@ wl_status ov_apply(Overlap &O, int prec, bool dagger, const Field out[2], const 
         e.X[1] = v[p];
         if (X1) e.X[2] = X1[p];
         if (X2) e.X[3] = X2[p];
-        const RedSpec r = red_dst ? red_spec(S, p == 0 ? RED_STORE : RED_ACCUM, red_dst) : no_red();
+        // with deflation the norm is taken after the exact low-mode part is added
+        const RedSpec r = red_dst && !O.D.nev ? red_spec(S, p == 0 ? RED_STORE : RED_ACCUM, red_dst) : no_red();
         WL_TRY(hop(S, prec, O.recon, false, p, out[p], y[1 - p], e, r, s));
+    }
+    if (O.D.nev) {
+        // + alpha b (g5) sum_i sign(lambda_i) xi_i <xi_i, in>: g5 eps for the operator, eps g5 for the adjoint
+        for (size_t k = 0; k < c.size(); ++k) z[k] = alpha * O.b * (O.D.lam[k / S.nvec] > 0 ? 1.0 : -1.0) * c[k];
+        WL_TRY(defl_axpy(S, O.D, prec, out, z, !dagger, s));
+        if (red_dst) {
+            WL_TRY(blas(S, BL_NORM2, prec, &out[0], 1, nullptr, red_spec(S, RED_STORE, red_dst), s));
+            WL_TRY(blas(S, BL_NORM2, prec, &out[1], 1, nullptr, red_spec(S, RED_ACCUM, red_dst), s));
+        }
     }
     return WL_OK;
 }
@@ -121,9 +139,14 @@ wl_status no_overlap(const double *a, const double *b, wl_gauge U, int nrhs)
 }
 
 wl_status setup(wl_gauge U, int nrhs, double rho, double mass, int degree, double lo, double hi, double scale,
-                int recon, const double *v0, hipStream_t s, Overlap *O)
+                int recon, const double *v0, int nev, const double *evecs, const double *evals, hipStream_t s,
+                Overlap *O)
 {
+    if (nev < 0 || nev > 64) return set_error(WL_ERR_ARG, "nev must be in [0, 64]");
+    if (nev > 0 && !evals) return set_error(WL_ERR_ARG, "null eigenvalues");
+    if (nev > 0) WL_TRY(check_field(evecs, U, nev, "evecs"));
     if (!(scale > 0)) WL_TRY(hw2_scale(U, rho, v0, s, &scale));
+    WL_TRY(defl_load(U, 1.0 / (8.0 - 2.0 * rho), nev, evecs, evals, s, &O->D));
     WL_TRY(get_set({SysEntry{U, nrhs, 1.0 / (8.0 - 2.0 * rho)}}, &O->S));
     std::fill(O->S->h_active.begin(), O->S->h_active.end(), 1);
     WL_TRY(O->S->upload_active(s));
@@ -143,7 +166,7 @@ extern "C" {
 
 wl_status overlap_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double rho, double mass,
                          int32_t degree, double lo, double hi, double scale, int32_t dagger, wl_prec prec,
-                         int32_t recon, void *stream)
+                         int32_t recon, int32_t nev, const double *evecs, const double *evals, void *stream)
 {
     clear_error();
     WL_TRY(common_checks(U, nrhs, rho, mass, degree, lo, hi, scale, prec, recon));
@@ -152,7 +175,7 @@ wl_status overlap_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs
     WL_TRY(no_overlap(in, out, U, nrhs));
     hipStream_t s = (hipStream_t)stream;
     Overlap O;
-    WL_TRY(setup(U, nrhs, rho, mass, degree, lo, hi, scale, recon, in, s, &O));
+    WL_TRY(setup(U, nrhs, rho, mass, degree, lo, hi, scale, recon, in, nev, evecs, evals, s, &O));
     ExecSet &S = *O.S;
     const double *cin[1] = {in};
     double *cout[1] = {out};
@@ -170,7 +193,8 @@ wl_status overlap_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs
 
 wl_status overlap_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, double rho, double mass,
                      int32_t degree, double lo, double hi, double scale, double tol, int32_t maxiter,
-                     wl_prec sloppy, int32_t recon, double delta, wl_solve_info *info, void *stream)
+                     wl_prec sloppy, int32_t recon, double delta, int32_t nev, const double *evecs,
+                     const double *evals, wl_solve_info *info, void *stream)
 {
     clear_error();
     const auto t0 = std::chrono::steady_clock::now();
@@ -185,7 +209,7 @@ wl_status overlap_cg(wl_gauge U, const double *eta, double *x, int32_t nrhs, dou
     WL_TRY(no_overlap(eta, x, U, nrhs));
     hipStream_t s = (hipStream_t)stream;
     Overlap O;
-    WL_TRY(setup(U, nrhs, rho, mass, degree, lo, hi, scale, recon, eta, s, &O));
+    WL_TRY(setup(U, nrhs, rho, mass, degree, lo, hi, scale, recon, eta, nev, evecs, evals, s, &O));
     ExecSet &S = *O.S;
     const int nv = S.nvec;
     const int P = sloppy;

@@ -270,6 +270,7 @@ ExecSet::~ExecSet()
         (void)hipFree(kv.second.n);
     }
     for (auto &kv : coefs) (void)hipFree(kv.second);
+    for (auto &kv : bufs) (void)hipFree(kv.second.first);
     for (auto &kv : d_sys) (void)hipFree(kv.second);
     for (auto &kv : layouts) {
         (void)hipFree(kv.second.d_vec);
@@ -282,6 +283,9 @@ ExecSet::~ExecSet()
     (void)hipFree(bad);
     (void)hipFree(hist);
     (void)hipHostFree(h_pinned);
+    (void)hipHostFree(h_masks);
+    for (auto &e : mask_ev)
+        if (e) (void)hipEventDestroy(e);
 }
 
 #define WL_ALLOC(ptr, bytes)                                                              \
@@ -325,6 +329,12 @@ wl_status ExecSet::init()
         h_pinned = nullptr;
         return set_error(WL_ERR_NOMEM, "cannot allocate pinned host memory");
     }
+    if (hipHostMalloc((void **)&h_masks, sizeof(int32_t) * kMaskRing * nvec, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        h_masks = nullptr;
+        return set_error(WL_ERR_NOMEM, "cannot allocate pinned host memory");
+    }
+    for (auto &e : mask_ev) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     WL_HIP(hipMemcpy(d_active, h_active.data(), sizeof(int32_t) * nvec, hipMemcpyHostToDevice));
     WL_HIP(hipMemset(counters, 0, sizeof(uint32_t) * nvec));
     WL_HIP(hipMemset(sc, 0, sizeof(double) * SC_N * nvec));
@@ -335,11 +345,15 @@ wl_status ExecSet::init()
 
 wl_status ExecSet::upload_active(hipStream_t s)
 {
-    int32_t *h = (int32_t *)(h_pinned + (size_t)(kHist + SC_N) * nvec);
-    // the previous upload from this buffer has completed: callers synchronise between uploads
+    // a ring of pinned staging slots: the upload is ordered on the stream and
+    // the host waits only when it reuses a slot whose copy is still pending
+    const int k = mask_next;
+    mask_next = (mask_next + 1) % kMaskRing;
+    WL_HIP(hipEventSynchronize(mask_ev[k]));
+    int32_t *h = h_masks + (size_t)k * nvec;
     std::copy(h_active.begin(), h_active.end(), h);
     WL_HIP(hipMemcpyAsync(d_active, h, sizeof(int32_t) * nvec, hipMemcpyHostToDevice, s));
-    WL_HIP(hipStreamSynchronize(s));
+    WL_HIP(hipEventRecord(mask_ev[k], s));
     return WL_OK;
 }
 
@@ -402,6 +416,24 @@ wl_status ExecSet::layout(int B, const Layout **out)
     WL_HIP(hipMemcpy(L.d_map, map.data(), sizeof(BlkMap) * map.size(), hipMemcpyHostToDevice));
     layouts[B] = L;
     *out = &layouts[B];
+    return WL_OK;
+}
+
+wl_status ExecSet::buffer(const std::string &name, size_t bytes, void **out)
+{
+    auto it = bufs.find(name);
+    if (it != bufs.end() && it->second.second >= bytes) {
+        *out = it->second.first;
+        return WL_OK;
+    }
+    if (it != bufs.end()) {
+        WL_HIP(hipFree(it->second.first));
+        bufs.erase(it);
+    }
+    void *p = nullptr;
+    WL_ALLOC(p, bytes);
+    bufs[name] = {p, bytes};
+    *out = p;
     return WL_OK;
 }
 
@@ -658,7 +690,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
 static const int kBlasBlock = 256;
 
 wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
-               hipStream_t s, bool use_active, int parity)
+               hipStream_t s, bool use_active, int parity, int bcast)
 {
     const SysDesc *sysd = nullptr;
     if (op == BL_CLOV_INV)
@@ -682,8 +714,10 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.nvec = S.nvec;
     a.red = red;
     a.parity = parity;
-    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2, 2};
+    a.bcast = bcast;
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2, 2, 3, 3, 0};
     if (op == BL_CLOV_INV) g_bytes_acc += clover_bytes(S, prec, use_active);
+    if (op == BL_ROT) g_bytes_acc += blas_bytes(S, prec, S.nvec + 1, use_active);
     if (op == BL_ACCUM)
         g_bytes_acc += blas_bytes(S, P_F64, 2, use_active) + blas_bytes(S, prec, 2, use_active);
     else

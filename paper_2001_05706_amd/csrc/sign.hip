@@ -192,9 +192,13 @@ wl_status wl_hw2_lmax(wl_gauge U, double rho, const double *v0, int32_t iters, d
 }
 
 wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t nrhs, double rho, int32_t degree,
-                            double lo, double hi, double scale, wl_prec prec, int32_t recon, void *stream)
+                            double lo, double hi, double scale, wl_prec prec, int32_t recon, int32_t nev,
+                            const double *evecs, const double *evals, void *stream)
 {
     clear_error();
+    if (nev < 0 || nev > 64) return set_error(WL_ERR_ARG, "nev must be in [0, 64]");
+    if (nev > 0 && !evals) return set_error(WL_ERR_ARG, "null eigenvalues");
+    if (nev > 0) WL_TRY(check_field(evecs, U, nev, "evecs"));
     WL_TRY(check_gauge(U));
     if (nrhs < 1) return set_error(WL_ERR_ARG, "nrhs must be >= 1");
     if (!(rho > 0 && rho < 4)) return set_error(WL_ERR_ARG, "rho must be in (0, 4)");
@@ -219,19 +223,33 @@ wl_status overlap_sign_cheb(wl_gauge U, const double *in, double *out, int32_t n
 
     if (!(scale > 0)) WL_TRY(hw2_scale(U, rho, in, s, &scale));
 
+    Deflation D;
+    WL_TRY(defl_load(U, 1.0 / (8.0 - 2.0 * rho), nev, evecs, evals, s, &D));
     Field v[2], w[2], y[2];
     for (int p = 0; p < 2; ++p) {
         WL_TRY(S->field("sg_v" + std::to_string(p), prec, &v[p]));
         WL_TRY(S->field("sg_w" + std::to_string(p), prec, &w[p]));
         WL_TRY(pack(*S, cin, p, v[p], s));
     }
+    // deflation: the polynomial acts on v - sum_i xi_i <xi_i, v>
+    std::vector<std::complex<double>> c, z;
+    if (D.nev) {
+        WL_TRY(defl_coeffs(*S, D, prec, v, c, s));
+        z.resize(c.size());
+        for (size_t k = 0; k < c.size(); ++k) z[k] = -c[k];
+        WL_TRY(defl_axpy(*S, D, prec, v, z, false, s));
+    }
     SignPlan P;
     WL_TRY(sign_plan(*S, rho, degree, lo, hi, scale, &P));
     WL_TRY(sign_poly(*S, prec, recon, P, v, y, s));
-    // out = s^{-1/2} H_W (p v)
+    // out = s^{-1/2} H_W (p v) (+ sum_i sign(lambda_i) xi_i <xi_i, v>)
     const double *orow = nullptr;
     WL_TRY(coef_table(*S, {P.rs * P.m, 0, 0, 0, -0.5 * P.rs}, &orow));
     WL_TRY(apply_hw(*S, prec, recon, w, y, orow, nullptr, s));
+    if (D.nev) {
+        for (size_t k = 0; k < c.size(); ++k) z[k] = (D.lam[k / S->nvec] > 0 ? 1.0 : -1.0) * c[k];
+        WL_TRY(defl_axpy(*S, D, prec, w, z, false, s));
+    }
     for (int p = 0; p < 2; ++p) WL_TRY(unpack(*S, cout, p, w[p], s));
     WL_HIP(hipStreamSynchronize(s));
     return WL_OK;

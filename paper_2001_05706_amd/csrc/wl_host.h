@@ -3,6 +3,7 @@
 // fields, the launch autotuner and the kernel timer.
 #pragma once
 
+#include <complex>
 #include <functional>
 #include <map>
 #include <memory>
@@ -113,7 +114,12 @@ public:
     wl_status layout(int B, const Layout **out);
     int32_t *d_active = nullptr;
     std::vector<int32_t> h_active;
+    // copy h_active to d_active, ordered on the stream (no host synchronisation)
     wl_status upload_active(hipStream_t s);
+    static constexpr int kMaskRing = 16;
+    int32_t *h_masks = nullptr;  // pinned staging slots of the mask uploads
+    hipEvent_t mask_ev[kMaskRing] = {};
+    int mask_next = 0;
 
     // reduction state (per vector unless noted)
     double *partials = nullptr;  // max slots over layouts (B = 64), 3 values each
@@ -129,6 +135,9 @@ public:
 
     // fields by name, allocated on first use
     wl_status field(const std::string &name, int prec, Field *out);
+    // device scratch by name, grown on demand (contents not kept across growth)
+    wl_status buffer(const std::string &name, size_t bytes, void **out);
+    std::map<std::string, std::pair<void *, size_t>> bufs;
 
     std::map<std::pair<int, int>, SysDesc *> d_sys;
     std::map<int, Layout> layouts;
@@ -158,8 +167,9 @@ RedSpec red_spec(ExecSet &S, int kind, double *dst, int nv = 1, int mode = RM_NO
 // out_p = epilogue(hop(in_{1-p})) on every active vector of the set
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int out_parity, const Field &out, const Field &in,
               const Epi &e, const RedSpec &red, hipStream_t s, bool use_active = true);
+// bcast: bit j marks field j as a single vector shared by every vector of the set
 wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
-               hipStream_t s, bool use_active = true, int parity = 0);
+               hipStream_t s, bool use_active = true, int parity = 0, int bcast = 0);
 wl_status convert(ExecSet &S, const Field &dst, const Field &src, hipStream_t s, bool use_active = true);
 // canonical <-> packed for one parity; canon[i] is the canonical field array of system i
 wl_status pack(ExecSet &S, const double *const *canon, int parity, const Field &f, hipStream_t s);
@@ -188,6 +198,25 @@ wl_status apply_hw(ExecSet &S, int prec, int recon, const Field out[2], const Fi
                    const RedSpec *red, hipStream_t s);
 wl_status power_lmax(ExecSet &S, double rho, int recon, int iters, const Field u[2], double *lmax, hipStream_t s);
 wl_status hw2_scale(wl_gauge U, double rho, const double *v0, hipStream_t s, double *scale);
+
+// ------------------------------------------------------------------ low-mode deflation (eigs.hip)
+
+// nev eigenpairs of H_W packed as the vectors of a single-system set
+struct Deflation {
+    int nev = 0;
+    ExecSet *E = nullptr;
+    std::vector<double> lam;  // eigenvalues of H_W
+    Field f64[2], f32[2];     // packed eigenvectors per parity, FP64 and FP32
+};
+// pack nev canonical eigenvectors (device) and their eigenvalues (host); nev = 0: none
+wl_status defl_load(wl_gauge U, double kappa, int nev, const double *evecs, const double *evals, hipStream_t s,
+                    Deflation *D);
+// c[i * nvec + v] = <xi_i, in_v> over both parities (host result)
+wl_status defl_coeffs(ExecSet &S, const Deflation &D, int prec, const Field in[2], std::vector<std::complex<double>> &c,
+                      hipStream_t s);
+// y_v += sum_i z[i * nvec + v] (g5) xi_i over both parities
+wl_status defl_axpy(ExecSet &S, const Deflation &D, int prec, const Field y[2], const std::vector<std::complex<double>> &z,
+                    bool g5, hipStream_t s);
 
 // ------------------------------------------------------------------ tuning and timing
 

@@ -17,7 +17,7 @@ struct BlasArgs {
     const double *s0;  // per-vector scalar (alpha or beta)
     const double *sc;  // scalar slots of the set (ScSlot), for complex scalars
     int32_t nvec;
-    int32_t pad2_;
+    int32_t bcast;     // bit j: field j is one vector shared by every vector of the set
     RedSpec red;
 };
 
@@ -59,6 +59,10 @@ enum BlasOp {
     BL_CDOT = 11,      // <a, b>                                                            f = {a, b}
     BL_G5COPY = 12,    // y = g5 x                                                          f = {y, x}
     BL_CLOV_INV = 13,  // y = A^{-1} x on parity `parity` (clover systems; a copy otherwise)  f = {y, x}
+    // deflation and block operations (single-system sets; complex scalars from s0):
+    BL_CAXPY = 14,     // y += z x, z = (s0[2v], s0[2v+1])                                  f = {y, x}
+    BL_CAXPY_G5 = 15,  // y += z g5 x                                                       f = {y, x}
+    BL_ROT = 16,       // y_v = sum_j T[j + nvec v] x_j, T complex (s0)                      f = {y, x}
 };
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
 // fixed-order sum of each active vector's block partials and the reduction's finishing step

@@ -63,6 +63,8 @@ enum RedKind {
     RED_BICG_OMEGA = 8,   // omega = (s0 + i s1) / s2
     RED_BICG_RHO = 9,     // rho = s0 + i s1; dst[v] = s2
     RED_BICG_INIT = 10,   // rho = rho_prev = s0 + i s1; alpha = omega = 1
+    RED_CSTORE = 11,      // dst[2v] = s0, dst[2v+1] = s1
+    RED_CACCUM = 12,      // dst[2v] += s0, dst[2v+1] += s1
 };
 
 // What the hop epilogue reduces (RedSpec::mode)

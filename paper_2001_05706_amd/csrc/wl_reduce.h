@@ -85,6 +85,14 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const doub
         WL_SC(SC_RHO_IM) = s[1];
         r.dst[v] = s[2];
         break;
+    case RED_CSTORE:
+        r.dst[2 * v] = s[0];
+        r.dst[2 * v + 1] = s[1];
+        break;
+    case RED_CACCUM:
+        r.dst[2 * v] += s[0];
+        r.dst[2 * v + 1] += s[1];
+        break;
     default: break;
     }
 #undef WL_SC

@@ -66,10 +66,14 @@ SIGNATURES = [
     ("wilson_clover_cg", _i32, [_P, _P, _P, _i32, _d, _d, _d, _i32, _i32, _i32, _d, ctypes.POINTER(WlSolveInfo), _P]),
     ("wilson_clover_bicgstab", _i32, [_P, _P, _P, _i32, _d, _d, _d, _i32, _i32, _i32, _d,
                                       ctypes.POINTER(WlSolveInfo), _P]),
-    ("overlap_sign_cheb", _i32, [_P, _P, _P, _i32, _d, _i32, _d, _d, _d, _i32, _i32, _P]),
-    ("overlap_dslash", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _i32, _i32, _i32, _P]),
-    ("overlap_cg", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _d, _i32, _i32, _i32, _d,
-                          ctypes.POINTER(WlSolveInfo), _P]),
+    ("overlap_sign_cheb", _i32, [_P, _P, _P, _i32, _d, _i32, _d, _d, _d, _i32, _i32, _i32, _P, ctypes.POINTER(_d),
+                                 _P]),
+    ("wl_hw_eigs", _i32, [_P, _d, _i32, _i32, _i32, _d, _i32, _d, _P, ctypes.POINTER(_d), ctypes.POINTER(_d),
+                          ctypes.POINTER(_i32), _P]),
+    ("overlap_dslash", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _i32, _i32, _i32, _i32, _P,
+                              ctypes.POINTER(_d), _P]),
+    ("overlap_cg", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _d, _d, _d, _d, _i32, _i32, _i32, _d, _i32, _P,
+                          ctypes.POINTER(_d), ctypes.POINTER(WlSolveInfo), _P]),
     ("wl_hw2_lmax", _i32, [_P, _d, _P, _i32, ctypes.POINTER(_d), _P]),
     ("wl_status_string", ctypes.c_char_p, [_i32]),
     ("wl_last_error", ctypes.c_char_p, []),
@@ -242,25 +246,49 @@ def wilson_clover_bicgstab(U: Gauge, eta, x, nrhs, kappa, csw, tol, maxiter, slo
                          delta, stream, check)
 
 
-def overlap_sign_cheb(U: Gauge, inp, out, nrhs, rho, degree, lo, hi, scale, prec="f32", recon=12, stream=None):
+def overlap_sign_cheb(U: Gauge, inp, out, nrhs, rho, degree, lo, hi, scale, prec="f32", recon=12, stream=None,
+                      evecs=None, evals=None):
+    nev, pe, pl = _defl(evecs, evals)
     return _check(lib().overlap_sign_cheb(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(rho),
                                           int(degree), float(lo), float(hi), float(scale), _prec(prec), int(recon),
-                                          _stream(stream)))
+                                          nev, pe, pl, _stream(stream)))
+
+
+def wl_hw_eigs(U: Gauge, rho, nev, nblock, degree, tol, maxiter, scale, evecs, stream=None, check=True):
+    """nev low eigenpairs of H_W into the device array evecs; returns (status, evals, resid, iters)."""
+    ev = (ctypes.c_double * int(nev))()
+    rs = (ctypes.c_double * int(nev))()
+    it = ctypes.c_int32()
+    st = lib().wl_hw_eigs(U.handle, float(rho), int(nev), int(nblock), int(degree), float(tol), int(maxiter),
+                          float(scale), _ptr(evecs, "evecs"), ev, rs, ctypes.byref(it), _stream(stream))
+    if check:
+        _check(st)
+    return st, list(ev), list(rs), it.value
+
+
+def _defl(evecs, evals):
+    """(nev, device pointer, host double array) of an optional deflation space."""
+    if evecs is None:
+        return 0, None, None
+    lam = [float(v) for v in evals]
+    return len(lam), _ptr(evecs, "evecs"), (ctypes.c_double * len(lam))(*lam)
 
 
 def overlap_dslash(U: Gauge, inp, out, nrhs, rho, mass, degree, lo, hi, scale, dagger=0, prec="f32", recon=12,
-                   stream=None):
+                   stream=None, evecs=None, evals=None):
+    nev, pe, pl = _defl(evecs, evals)
     return _check(lib().overlap_dslash(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(rho),
                                        float(mass), int(degree), float(lo), float(hi), float(scale), int(dagger),
-                                       _prec(prec), int(recon), _stream(stream)))
+                                       _prec(prec), int(recon), nev, pe, pl, _stream(stream)))
 
 
 def overlap_cg(U: Gauge, eta, x, nrhs, rho, mass, degree, lo, hi, scale, tol, maxiter, sloppy="f32", recon=12,
-               delta=1e-3, stream=None, check=True):
+               delta=1e-3, stream=None, check=True, evecs=None, evals=None):
+    nev, pe, pl = _defl(evecs, evals)
     infos = (WlSolveInfo * int(nrhs))()
     st = lib().overlap_cg(U.handle, _ptr(eta, "eta"), _ptr(x, "x"), int(nrhs), float(rho), float(mass),
                           int(degree), float(lo), float(hi), float(scale), float(tol), int(maxiter),
-                          _prec(sloppy), int(recon), float(delta), infos, _stream(stream))
+                          _prec(sloppy), int(recon), float(delta), nev, pe, pl, infos, _stream(stream))
     res = [i.as_dict() for i in infos]
     if check:
         _check(st, res)

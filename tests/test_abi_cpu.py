@@ -67,5 +67,13 @@ def test_validation_before_device_work(w):
     info = (w.WlSolveInfo * 1)()
     assert lib.wilson_cg(None, None, None, 1, 0.1, 1e-10, 10, 1, 12, 0.1, info, None) == w.WL_ERR_ARG
     assert lib.wilson_cg_multi(0, None, None, None, None, None, 1e-10, 10, 1, 12, 0.1, info, None) == w.WL_ERR_ARG
-    assert lib.overlap_sign_cheb(None, None, None, 1, 1.5, 10, 0.01, 1.0, 1.0, 1, 12, None) == w.WL_ERR_ARG
+    assert lib.overlap_sign_cheb(None, None, None, 1, 1.5, 10, 0.01, 1.0, 1.0, 1, 12, 0, None, None, None) == w.WL_ERR_ARG
+    assert lib.overlap_dslash(None, None, None, 1, 1.5, 0.1, 10, 0.01, 1.0, 1.0, 0, 1, 12, 0, None, None,
+                              None) == w.WL_ERR_ARG
+    assert lib.overlap_cg(None, None, None, 1, 1.5, 0.1, 10, 0.01, 1.0, 1.0, 1e-8, 10, 1, 12, 1e-3, 0, None, None,
+                          info, None) == w.WL_ERR_ARG
+    assert lib.wilson_clover_cg(None, None, None, 1, 0.12, 1.0, 1e-10, 10, 1, 12, 0.1, info, None) == w.WL_ERR_ARG
+    assert lib.wilson_clover_dslash(None, None, None, 1, 0.12, 1.0, 0, 1, 12, None) == w.WL_ERR_ARG
+    ev = (ctypes.c_double * 1)()
+    assert lib.wl_hw_eigs(None, 1.5, 1, 2, 8, 1e-8, 10, 1.0, None, ev, ev, None, None) == w.WL_ERR_ARG
     assert lib.wl_bench_copy(10, 1, None, None) == w.WL_ERR_ARG
