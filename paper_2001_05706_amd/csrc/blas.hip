@@ -399,6 +399,31 @@ __global__ __launch_bounds__(1024) void k_red_finalize(RedSpec r, const VecDesc 
     if (threadIdx.x == 0) red_finalize(r, v, tot);
 }
 
+// Deferred |r|^2 of k iterations: block (v, j) sums row j of the per-iteration
+// partials of vector v in a fixed order into hist[j * nvec + v].
+__global__ __launch_bounds__(256) void k_hist_finalize(const double *partials, size_t row, const VecDesc *vec,
+                                                       const int32_t *active, int nvec, double *hist, int32_t *bad)
+{
+    const int v = blockIdx.x, j = blockIdx.y;
+    if (active && !active[v]) return;
+    const VecDesc vd = vec[v];
+    const double *p = partials + (size_t)j * row + vd.pslot0;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < vd.nblk; i += blockDim.x) s += p[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        hist[(size_t)j * nvec + v] = s;
+        if (!isfinite(s) && bad) bad[v] |= 1;
+    }
+}
+
+hipError_t launch_hist_finalize(const double *partials, size_t row, const VecDesc *vec, const int32_t *active, int nvec,
+                                int k, double *hist, int32_t *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hist_finalize, dim3(nvec, k), dim3(256), 0, s, partials, row, vec, active, nvec, hist, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s)
 {
     hipLaunchKernelGGL(k_red_finalize, dim3(nvec), dim3(1024), 0, s, r, vec, active);

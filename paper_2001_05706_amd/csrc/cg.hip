@@ -149,9 +149,11 @@ struct Cg {
         return WL_OK;
     }
 
-    // one iteration in the sloppy precision; hist_row receives |r|^2
-    wl_status iteration(double *hist_row)
+    // iteration j of a chunk in the sloppy precision; history row j receives |r|^2
+    // (CGNR: its block partials are summed for the whole chunk by hist_finalize)
+    wl_status iteration(int j)
     {
+        double *hist_row = S.hist + (size_t)j * S.nvec;
         if (method == M_BICGSTAB) {
             // p = r + beta (p - omega v);  v = M p, alpha = rho / <rhat, v>;  s = r - alpha v;
             // t = M s, omega = <t, s> / |t|^2;  x += alpha p + omega s;  r = s - omega t, rho = <rhat, r>
@@ -171,7 +173,10 @@ struct Cg {
         }
         WL_TRY(apply_M(sloppy, recon, false, q, p, tl, red_spec(S, RED_ALPHA, nullptr)));
         Field f[4] = {xl, p, rl, q};
-        WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(SC_ALPHA), red_spec(S, RED_STORE, hist_row), s));
+        RedSpec rr = red_spec(S, RED_STORE, hist_row);
+        rr.partials = S.hist_partials + (size_t)j * S.max_pslots;
+        rr.defer = 1;
+        WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(SC_ALPHA), rr, s));
         WL_TRY(apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_BETA, nullptr)));
         Field g[2] = {p, sv};
         WL_TRY(blas(S, BL_XPAY, sloppy, g, 2, S.scal(SC_BETA), no_red(), s));
@@ -234,7 +239,8 @@ struct Cg {
     wl_status chunk(int k)
     {
         if (!use_graphs || prof().on) {
-            for (int j = 0; j < k; ++j) WL_TRY(iteration(S.hist + (size_t)j * S.nvec));
+            for (int j = 0; j < k; ++j) WL_TRY(iteration(j));
+            if (method == M_CGNR) WL_TRY(hist_finalize(S, k, s));
             return WL_OK;
         }
         const std::string key = "cg/" + std::to_string(method) + "/" + std::to_string(k) + "/" +
@@ -250,7 +256,8 @@ struct Cg {
             s = cs;
             WL_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
             wl_status st = WL_OK;
-            for (int j = 0; j < k && st == WL_OK; ++j) st = iteration(S.hist + (size_t)j * S.nvec);
+            for (int j = 0; j < k && st == WL_OK; ++j) st = iteration(j);
+            if (st == WL_OK && method == M_CGNR) st = hist_finalize(S, k, s);
             hipGraph_t g = nullptr;
             hipError_t ce = hipStreamEndCapture(cs, &g);
             s = user;

@@ -282,6 +282,7 @@ ExecSet::~ExecSet()
     (void)hipFree(sc);
     (void)hipFree(bad);
     (void)hipFree(hist);
+    (void)hipFree(hist_partials);
     (void)hipHostFree(h_pinned);
     (void)hipHostFree(h_masks);
     for (auto &e : mask_ev)
@@ -324,6 +325,7 @@ wl_status ExecSet::init()
     WL_ALLOC(sc, sizeof(double) * SC_N * nvec);
     WL_ALLOC(bad, sizeof(int32_t) * nvec);
     WL_ALLOC(hist, sizeof(double) * kHist * nvec);
+    WL_ALLOC(hist_partials, sizeof(double) * kHist * max_pslots);
     if (hipHostMalloc((void **)&h_pinned, sizeof(double) * (kHist + SC_N + 1) * nvec + 64, 0) != hipSuccess) {
         (void)hipGetLastError();
         h_pinned = nullptr;
@@ -723,7 +725,16 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     else
         g_bytes_acc += blas_bytes(S, prec, passes[op], use_active);
     WL_HIP(launch_blas(op, prec, a, kBlasBlock, s));
-    if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, a.active, S.nvec, s));
+    if (red.kind != RED_NONE && !red.defer) WL_HIP(launch_red_finalize(red, L->d_vec, a.active, S.nvec, s));
+    return WL_OK;
+}
+
+wl_status hist_finalize(ExecSet &S, int k, hipStream_t s)
+{
+    const Layout *L = nullptr;
+    WL_TRY(S.layout(kBlasBlock, &L));
+    WL_HIP(launch_hist_finalize(S.hist_partials, (size_t)S.max_pslots, L->d_vec, S.d_active, S.nvec, k, S.hist, S.bad,
+                                s));
     return WL_OK;
 }
 

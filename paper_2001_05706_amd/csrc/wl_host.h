@@ -127,6 +127,7 @@ public:
     double *sc = nullptr;        // scalar arena, see SC_* below
     int32_t *bad = nullptr;
     double *hist = nullptr;      // residual history: [kHist][nvec]
+    double *hist_partials = nullptr;  // deferred block partials of the history: [kHist][max_pslots]
     double *h_pinned = nullptr;  // pinned host mirror of hist, scalars and flags
     static constexpr int kHist = 64;
 
@@ -175,6 +176,9 @@ wl_status convert(ExecSet &S, const Field &dst, const Field &src, hipStream_t s,
 wl_status pack(ExecSet &S, const double *const *canon, int parity, const Field &f, hipStream_t s);
 wl_status unpack(ExecSet &S, double *const *canon, int parity, const Field &f, hipStream_t s);
 wl_status zero_canon(ExecSet &S, double *const *canon, int parity, hipStream_t s);
+
+// sum the deferred |r|^2 partials of the last k iterations into hist rows 0..k-1
+wl_status hist_finalize(ExecSet &S, int k, hipStream_t s);
 
 // device coefficient tables [nsys][5], cached by content
 wl_status coef_table(ExecSet &S, const std::vector<double> &c, const double **out);

@@ -67,6 +67,9 @@ enum BlasOp {
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
 // fixed-order sum of each active vector's block partials and the reduction's finishing step
 hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s);
+// k deferred |r|^2 rows (partials row j at partials + j * row) into hist[j * nvec + v]
+hipError_t launch_hist_finalize(const double *partials, size_t row, const VecDesc *vec, const int32_t *active, int nvec,
+                                int k, double *hist, int32_t *bad, hipStream_t s);
 // y (prec_dst) = x (prec_src), f = {y, x}
 hipError_t launch_convert(int prec_dst, int prec_src, const BlasArgs &a, int block, hipStream_t s);
 

@@ -83,6 +83,8 @@ struct RedSpec {
     double *sc;          // scalar slots (ScSlot)
     double *dst;         // RED_STORE / RED_ACCUM / RED_BICG_RHO target, indexed by vector
     int32_t *bad;        // per-vector non-finite flag (bit 0)
+    int32_t defer;       // 1: leave the partials for a later finishing pass (no finishing launch)
+    int32_t pad_;
 };
 
 // Linear combination applied to the hopping term at the output site:
