@@ -25,16 +25,20 @@ namespace wl {
 //   3: fence 2, 4 waves (FP64: 2), cached links
 //   4: fence 4, 4 waves, cached links -- twice the bytes in flight per wave
 //   5: fence 4, 5 waves, cached links
+//   6: as 3, but the waves of a block serve consecutive right-hand sides of one
+//      system on the same 64 sites, so the links they share hit in the CU's L1
+//      (multi-RHS sets; launched on the layouts of `ExecSet::layout(-G)`)
 // Variants 4 and 5 exist for FP16/BF16 storage only (FP32 and FP64 operands of
 // four directions do not fit the registers); for those they repeat variant 3.
 template <int SP, int VAR> struct HopVar {
     static constexpr bool half = SP == P_F16 || SP == P_BF16;
-    static constexpr int fence = VAR == 0 || VAR == 3 ? 2 : (VAR >= 4 ? (half ? 4 : 2) : 1);
+    static constexpr int fence = VAR == 0 || VAR == 3 || VAR == 6 ? 2 : (VAR >= 4 ? (half ? 4 : 2) : 1);
     static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR >= 3 ? 2 : 3)
-                                             : (VAR == 0 || VAR == 3 || VAR == 4 ? 4 : VAR == 2 ? 6 : 5);
+                                             : (VAR == 0 || VAR == 3 || VAR == 4 || VAR == 6 ? 4 : VAR == 2 ? 6 : 5);
     static constexpr bool nt = VAR < 3;
+    static constexpr bool rhs_waves = VAR == 6;
 };
-constexpr int kHopVariants = 6;
+constexpr int kHopVariants = 7;
 
 template <int SP, int GP, int R, bool DAG, int VAR, bool CLOV>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves))) void k_hop(HopArgs a)
@@ -43,17 +47,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     using CH = typename SpinorFmt<SP>::chunk;
     constexpr int NC = SpinorFmt<SP>::nchunk;
 
+    constexpr bool RW = HopVar<SP, VAR>::rhs_waves;
     const int lb = xcd_remap(blockIdx.x, a.nblocks);
     const BlkMap bm = a.map[lb];
-    if (a.active && !a.active[bm.v]) return;
+    int v = bm.v, cb;
+    bool valid = true;
+    if constexpr (RW) {
+        // wave w serves vector bm.v + w (when it is a further rhs of the same system) on 64 sites
+        // wave-uniform: keep the vector's descriptors in scalar registers
+        const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+        v = bm.v + w;
+        valid = v < a.nvec && a.vec[v].sys == a.vec[bm.v].sys && (!a.active || a.active[v]);
+        cb = bm.lblk * 64 + ((int)threadIdx.x & 63);
+    } else {
+        if (a.active && !a.active[bm.v]) return;
+        cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
+    }
     const unsigned long long t_start = a.stamps ? (unsigned long long)wall_clock64() : 0ull;
-    const VecDesc vd = a.vec[bm.v];
+    const VecDesc vd = a.vec[valid ? v : bm.v];
     const SysDesc sd = a.sys[vd.sys];
-    const int cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
     const size_t voff = (size_t)vd.site_off * NC;
 
     double rv[3] = {0.0, 0.0, 0.0};
-    if (cb < sd.Vh) {
+    if (valid && cb < sd.Vh) {
         HopSite hs;
         hs.in = (const CH *)a.in + voff;
         hs.in_norm = a.in_norm ? a.in_norm + vd.site_off : nullptr;
@@ -119,7 +135,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
             }
         }
     }
-    if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+    if constexpr (RW) {
+        if (a.red.kind != RED_NONE && valid) wave_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+    } else {
+        if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+    }
     if (a.stamps) {
         // the block's work ends when its last wave ends
         __syncthreads();
@@ -169,11 +189,12 @@ static hipError_t launch_hop_t(int var, bool dag, bool clov, const HopArgs &a, i
     case 3: return launch_hop_v<SP, GP, R, 3>(dag, clov, a, block, s, e0, e1);
     case 4: return launch_hop_v<SP, GP, R, 4>(dag, clov, a, block, s, e0, e1);
     case 5: return launch_hop_v<SP, GP, R, 5>(dag, clov, a, block, s, e0, e1);
+    case 6: return launch_hop_v<SP, GP, R, 6>(dag, clov, a, block, s, e0, e1);
     }
     return hipErrorInvalidValue;
 }
 
-int hop_variants(int prec) { return prec == P_F16 || prec == P_BF16 ? kHopVariants : 4; }
+int hop_variants(int prec) { (void)prec; return kHopVariants; }
 
 hipError_t launch_hop(int prec, int recon, bool dag, bool clov, int var, const HopArgs &a, int block, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1)

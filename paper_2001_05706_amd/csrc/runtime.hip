@@ -393,12 +393,14 @@ wl_status ExecSet::layout(int B, const Layout **out)
     }
     Layout L;
     L.B = B;
+    // B < 0: blocks of -B right-hand sides (one wave each) on 64 sites
+    const int G = B < 0 ? -B : 1, sites = B < 0 ? 64 : B;
     std::vector<VecDesc> hv = vec;
     std::vector<BlkMap> map;
     int ps = 0, vbase = 0;
     for (size_t i = 0; i < systems.size(); ++i) {
         const int nrhs = systems[i].nrhs;
-        const int nb = (systems[i].g->geom.Vh + B - 1) / B;
+        const int nb = (systems[i].g->geom.Vh + sites - 1) / sites;
         for (int r = 0; r < nrhs; ++r) {
             hv[vbase + r].nblk = nb;
             hv[vbase + r].pslot0 = ps;
@@ -406,7 +408,7 @@ wl_status ExecSet::layout(int B, const Layout **out)
         }
         // logical order (system, site block, rhs): right-hand sides sharing links are adjacent
         for (int b = 0; b < nb; ++b)
-            for (int r = 0; r < nrhs; ++r) map.push_back(BlkMap{vbase + r, b});
+            for (int r = 0; r < nrhs; r += G) map.push_back(BlkMap{vbase + r, b});
         vbase += nrhs;
     }
     L.nblocks = (int)map.size();
@@ -592,10 +594,25 @@ std::string hop_key(const ExecSet &S, int prec, int recon, bool dag)
 // (variant, block size) pairs encoded as variant * 1024 + block
 std::vector<int> hop_candidates(int prec)
 {
+    const bool half = prec == P_F16 || prec == P_BF16;
     std::vector<int> c;
-    for (int v = 0; v < hop_variants(prec); ++v)
+    for (int v = 0; v < hop_variants(prec); ++v) {
+        if ((v == 4 || v == 5) && !half) continue;  // four directions in flight: half precision only
+        if (v == 6) {
+            for (int b : {256, 512}) c.push_back(v * 1024 + b);  // 4 or 8 right-hand sides per block
+            continue;
+        }
         for (int b : {64, 128, 256, 512}) c.push_back(v * 1024 + b);
+    }
     return c;
+}
+
+// the block layout a hop launch configuration runs on: variant 6 blocks hold
+// B / 64 right-hand sides of 64 sites each
+static wl_status hop_layout(ExecSet &S, int cfg, const Layout **L)
+{
+    const int var = cfg / 1024, B = cfg % 1024;
+    return S.layout(var == 6 ? -(B / 64) : B, L);
 }
 
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
@@ -612,6 +629,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         a.active = use_active ? S.d_active : nullptr;
         a.nblocks = L->nblocks;
         a.parity = par;
+        a.nvec = S.nvec;
         a.in = in.p;
         a.in_norm = in.n;
         a.out = out.p;
@@ -632,15 +650,19 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
     if (clov)  // the clover epilogue needs the registers of the two-direction variants (0 and 3)
         cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 == 1 || c / 1024 == 2; }),
                     cands.end());
+    int max_nrhs = 0;
+    for (auto &e : S.systems) max_nrhs = std::max(max_nrhs, e.nrhs);
+    if (max_nrhs < 2)  // right-hand-side blocks need several right-hand sides
+        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 == 6; }), cands.end());
     if (cands.empty()) cands = hop_candidates(prec);
     const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;
-        if (S.layout(c % 1024, &L) != WL_OK) return hipErrorOutOfMemory;
+        if (hop_layout(S, c, &L) != WL_OK) return hipErrorOutOfMemory;
         return launch_hop(prec, recon, dag, clov, c / 1024, mk(L, no_red()), c % 1024, s);
     });
     const int B = cfg % 1024, var = cfg / 1024;
     const Layout *L = nullptr;
-    WL_TRY(S.layout(B, &L));
+    WL_TRY(hop_layout(S, cfg, &L));
     const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active) +
                          (clov ? ((e.clov & EPI_CLOV_X0) ? 1 : 0) + ((e.clov & EPI_CLOV_INV) ? 1 : 0) : 0) *
                              clover_bytes(S, prec, use_active);
@@ -1076,7 +1098,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
         cfg = tuned_block(hop_key(*S, prec, recon, false), hop_candidates(prec), s, [](int) { return hipSuccess; });
         B = cfg % 1024;
-        if (st == WL_OK) st = S->layout(B, &L);
+        if (st == WL_OK) st = hop_layout(*S, cfg, &L);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == WL_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -1090,6 +1112,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
             a.active = nullptr;
             a.nblocks = L->nblocks;
             a.parity = parity;
+            a.nvec = S->nvec;
             a.in = fin[k].p;
             a.in_norm = fin[k].n;
             a.out = fout[k].p;

@@ -222,29 +222,19 @@ WL_HD void load_spinor(const void *base, const float *norm, int stride, int cb,
     }
 }
 
-// As load_spinor, but FP16/BF16 values are returned site-normalised with the
-// site norm in *nrm (1 for FP64/FP32), so that a caller can apply the norm
-// after a linear step that shrinks the data (the hop's spin projection).
+// The 12 packed complex words of a half-precision site and its norm.
 template <int P>
-WL_HD void load_spinor_unscaled(const void *base, const float *norm, int stride, int cb,
-                                typename SpinorFmt<P>::real v[24], typename SpinorFmt<P>::real *nrm)
+WL_HD void load_spinor_words(const void *base, const float *norm, int stride, int cb, uint32_t q[12], float *nrm)
 {
     using CH = typename SpinorFmt<P>::chunk;
-    if constexpr (P == P_F64 || P == P_F32) {
-        load_spinor<P>(base, norm, stride, cb, v);
-        *nrm = 1;
-    } else {
-        *nrm = *row_elem<float>(norm, 0, 0, cb);
+    *nrm = *row_elem<float>(norm, 0, 0, cb);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            uint4 w = *row_elem<CH>(base, c, stride, cb);
-            uint32_t q[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                v[8 * c + 2 * k] = lo16_to_float<P>(q[k]);
-                v[8 * c + 2 * k + 1] = hi16_to_float<P>(q[k]);
-            }
-        }
+    for (int c = 0; c < 3; ++c) {
+        uint4 w = *row_elem<CH>(base, c, stride, cb);
+        q[4 * c] = w.x;
+        q[4 * c + 1] = w.y;
+        q[4 * c + 2] = w.z;
+        q[4 * c + 3] = w.w;
     }
 }
 
@@ -326,12 +316,14 @@ WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
         // row2 = conj(row0 x row1): u2k = conj(u0i u1j - u0j u1i), (k, i, j) cyclic
         auto cross = [](cpx<T> a, cpx<T> b, cpx<T> c, cpx<T> d) -> cpx<T> {
             if constexpr (sizeof(T) == 4) {
-                // FP32 arithmetic: chains of fused multiply-adds (fewer instructions)
-                T re = a.re * b.re;
+                // FP32 arithmetic: chains of fused multiply-adds (fewer instructions);
+                // each chain opens with an fma on zero so that half-precision
+                // operands enter the mixed-precision fma without a conversion
+                T re = fmadd(a.re, b.re, T(0));
                 re = fmadd(-a.im, b.im, re);
                 re = fmadd(-c.re, d.re, re);
                 re = fmadd(c.im, d.im, re);
-                T im = c.re * d.im;
+                T im = fmadd(c.re, d.im, T(0));
                 im = fmadd(c.im, d.re, im);
                 im = fmadd(-a.re, b.im, im);
                 im = fmadd(-a.im, b.re, im);
@@ -511,42 +503,108 @@ WL_HD void project(const T v[24], cpx<T> h0[3], cpx<T> h1[3])
     }
 }
 
-// f (a + s b) for s = +1, -1, +i, -i (S = 0, 1, 2, 3): one multiply and one
-// fused multiply-add per real output, so that half-precision inputs can enter
-// the mixed-precision fma directly
-template <int S, class T> WL_HD cpx<T> comb_scaled(cpx<T> a, cpx<T> b, T f, T nf)
+// ---- half-precision projection straight from the packed words
+//
+// A half-precision spinor word holds one complex number (real part in the low
+// 16 bits).  a_h + s b_h of two such halves is formed in FP32 without separate
+// conversions: FP16 through one mixed-precision fma (a * 1 + (+-b), each half
+// selected in place), BF16 by moving the half to the top of an FP32 word.
+
+template <int P, int H> WL_HD float half_part(uint32_t w)
 {
-    if constexpr (S == 0) return {fmadd(a.re, f, b.re * f), fmadd(a.im, f, b.im * f)};
-    if constexpr (S == 1) return {fmadd(a.re, f, b.re * nf), fmadd(a.im, f, b.im * nf)};
-    if constexpr (S == 2) return {fmadd(a.re, f, b.im * nf), fmadd(a.im, f, b.re * f)};
-    return {fmadd(a.re, f, b.im * f), fmadd(a.im, f, b.re * nf)};
+    if constexpr (P == P_F16) return H ? hi16_to_float<P>(w) : lo16_to_float<P>(w);
+    union { uint32_t u; float f; } c;
+    c.u = H ? (w & 0xFFFF0000u) : (w << 16);
+    return c.f;
 }
 
-// f P psi (the projection of `project`, scaled by f)
-template <int MU, int SG, class T>
-WL_HD void project_scaled(const T v[24], T f, cpx<T> h0[3], cpx<T> h1[3])
+template <int P, int HA, int HB, bool NEG> WL_HD float half_sum(uint32_t a, uint32_t b)
 {
-    const T nf = -f;
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (P == P_F16) {
+        float d;
+        // op_sel picks the half of each word, op_sel_hi marks sources 0 and 2 as FP16;
+        // the 1.0 multiplier sits in a scalar register (an FP32 operand)
+        if constexpr (NEG)
+            asm("v_fma_mix_f32 %0, %1, %2, -%3 op_sel:[%4,0,%5] op_sel_hi:[1,0,1]"
+                : "=v"(d) : "v"(a), "s"(1.0f), "v"(b), "i"(HA), "i"(HB));
+        else
+            asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[%4,0,%5] op_sel_hi:[1,0,1]"
+                : "=v"(d) : "v"(a), "s"(1.0f), "v"(b), "i"(HA), "i"(HB));
+        return d;
+    }
+#endif
+    const float x = half_part<P, HA>(a), y = half_part<P, HB>(b);
+    return NEG ? x - y : x + y;
+}
+
+// a + s b of two packed complex words, s = +1, -1, +i, -i (S = 0, 1, 2, 3)
+template <int P, int S> WL_HD cpx<float> half_comb(uint32_t a, uint32_t b)
+{
+    if constexpr (S == 0) return {half_sum<P, 0, 0, false>(a, b), half_sum<P, 1, 1, false>(a, b)};
+    if constexpr (S == 1) return {half_sum<P, 0, 0, true>(a, b), half_sum<P, 1, 1, true>(a, b)};
+    // a + i b = (a.re - b.im, a.im + b.re);  a - i b = (a.re + b.im, a.im - b.re)
+    if constexpr (S == 2) return {half_sum<P, 0, 1, true>(a, b), half_sum<P, 1, 0, false>(a, b)};
+    return {half_sum<P, 0, 1, false>(a, b), half_sum<P, 1, 0, true>(a, b)};
+}
+
+// P psi (the projection of `project`) of a half-precision spinor given as its
+// 12 packed complex words, site norm not applied
+template <int P, int MU, int SG>
+WL_HD void project_half(const uint32_t q[12], cpx<float> h0[3], cpx<float> h1[3])
+{
     constexpr int ADD = 0, SUB = 1, ADD_I = 2, SUB_I = 3;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        cpx<T> p0{v[2 * (0 + c)], v[2 * (0 + c) + 1]};
-        cpx<T> p1{v[2 * (3 + c)], v[2 * (3 + c) + 1]};
-        cpx<T> p2{v[2 * (6 + c)], v[2 * (6 + c) + 1]};
-        cpx<T> p3{v[2 * (9 + c)], v[2 * (9 + c) + 1]};
+        const uint32_t p0 = q[0 + c], p1 = q[3 + c], p2 = q[6 + c], p3 = q[9 + c];
         if constexpr (MU == 0) {
-            h0[c] = comb_scaled<(SG > 0 ? ADD_I : SUB_I)>(p0, p3, f, nf);
-            h1[c] = comb_scaled<(SG > 0 ? ADD_I : SUB_I)>(p1, p2, f, nf);
+            h0[c] = half_comb<P, (SG > 0 ? ADD_I : SUB_I)>(p0, p3);
+            h1[c] = half_comb<P, (SG > 0 ? ADD_I : SUB_I)>(p1, p2);
         } else if constexpr (MU == 1) {
-            h0[c] = comb_scaled<(SG > 0 ? SUB : ADD)>(p0, p3, f, nf);
-            h1[c] = comb_scaled<(SG > 0 ? ADD : SUB)>(p1, p2, f, nf);
+            h0[c] = half_comb<P, (SG > 0 ? SUB : ADD)>(p0, p3);
+            h1[c] = half_comb<P, (SG > 0 ? ADD : SUB)>(p1, p2);
         } else if constexpr (MU == 2) {
-            h0[c] = comb_scaled<(SG > 0 ? ADD_I : SUB_I)>(p0, p2, f, nf);
-            h1[c] = comb_scaled<(SG > 0 ? SUB_I : ADD_I)>(p1, p3, f, nf);
+            h0[c] = half_comb<P, (SG > 0 ? ADD_I : SUB_I)>(p0, p2);
+            h1[c] = half_comb<P, (SG > 0 ? SUB_I : ADD_I)>(p1, p3);
         } else {
-            h0[c] = comb_scaled<(SG > 0 ? ADD : SUB)>(p0, p2, f, nf);
-            h1[c] = comb_scaled<(SG > 0 ? ADD : SUB)>(p1, p3, f, nf);
+            h0[c] = half_comb<P, (SG > 0 ? ADD : SUB)>(p0, p2);
+            h1[c] = half_comb<P, (SG > 0 ? ADD : SUB)>(p1, p3);
         }
+    }
+}
+
+// acc += f P psi given U h0, U h1 of the unscaled projection: the factor f
+// (site norm and boundary sign) rides on the accumulating fma
+template <int MU, int SG, class T>
+WL_HD void reconstruct_add_scaled(T acc[24], const cpx<T> g0[3], const cpx<T> g1[3], T f)
+{
+    const T nf = -f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        acc[2 * (0 + c)] = fmadd(g0[c].re, f, acc[2 * (0 + c)]);
+        acc[2 * (0 + c) + 1] = fmadd(g0[c].im, f, acc[2 * (0 + c) + 1]);
+        acc[2 * (3 + c)] = fmadd(g1[c].re, f, acc[2 * (3 + c)]);
+        acc[2 * (3 + c) + 1] = fmadd(g1[c].im, f, acc[2 * (3 + c) + 1]);
+        // rows 2, 3 as in reconstruct_add, each term carrying +f or -f
+        T r2re, r2im, r3re, r3im;
+        T s2re, s2im, s3re, s3im;
+        if constexpr (MU == 0) {
+            r2re = g1[c].im; r2im = g1[c].re; s2re = SG > 0 ? f : nf; s2im = SG > 0 ? nf : f;
+            r3re = g0[c].im; r3im = g0[c].re; s3re = SG > 0 ? f : nf; s3im = SG > 0 ? nf : f;
+        } else if constexpr (MU == 1) {
+            r2re = g1[c].re; r2im = g1[c].im; s2re = s2im = SG > 0 ? f : nf;
+            r3re = g0[c].re; r3im = g0[c].im; s3re = s3im = SG > 0 ? nf : f;
+        } else if constexpr (MU == 2) {
+            r2re = g0[c].im; r2im = g0[c].re; s2re = SG > 0 ? f : nf; s2im = SG > 0 ? nf : f;
+            r3re = g1[c].im; r3im = g1[c].re; s3re = SG > 0 ? nf : f; s3im = SG > 0 ? f : nf;
+        } else {
+            r2re = g0[c].re; r2im = g0[c].im; s2re = s2im = SG > 0 ? f : nf;
+            r3re = g1[c].re; r3im = g1[c].im; s3re = s3im = SG > 0 ? f : nf;
+        }
+        acc[2 * (6 + c)] = fmadd(r2re, s2re, acc[2 * (6 + c)]);
+        acc[2 * (6 + c) + 1] = fmadd(r2im, s2im, acc[2 * (6 + c) + 1]);
+        acc[2 * (9 + c)] = fmadd(r3re, s3re, acc[2 * (9 + c)]);
+        acc[2 * (9 + c) + 1] = fmadd(r3im, s3im, acc[2 * (9 + c) + 1]);
     }
 }
 
@@ -610,13 +668,9 @@ WL_HD void su3_mul(const cpx<T> u[3][3], const cpx<T> h[3], cpx<T> g[3])
             const cpx<T> w = ADJ ? u[b][a] : u[a][b];
             // U h: (w.re h.re - w.im h.im, w.re h.im + w.im h.re); U^dagger: conj(w)
             const T wi = ADJ ? -w.im : w.im;
-            if (b == 0) {
-                re = w.re * h[b].re;
-                im = w.re * h[b].im;
-            } else {
-                re = fmadd(w.re, h[b].re, re);
-                im = fmadd(w.re, h[b].im, im);
-            }
+            // (the first term is an fma on zero as well: see load_link)
+            re = fmadd(w.re, h[b].re, re);
+            im = fmadd(w.re, h[b].im, im);
             re = fmadd(-wi, h[b].im, re);
             im = fmadd(wi, h[b].re, im);
         }
@@ -653,19 +707,23 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
     }
     const int ncb = (nx >> 1) + d.Lxh * (ny + d.L[1] * (nz + d.L[2] * nt));
 
-    T v[24], nrm;
-    load_spinor_unscaled<SP>(a.in, a.in_norm, a.stride, ncb, v, &nrm);
     // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
     constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
+    constexpr bool HALF = SP == P_F16 || SP == P_BF16;
     cpx<T> h0[3], h1[3];
-    if constexpr (SP == P_F16 || SP == P_BF16) {
-        // site norm of the half-precision neighbour and the boundary sign,
-        // folded into the projection
-        project_scaled<MU, SG>(v, flip ? -nrm : nrm, h0, h1);
+    T f = 1;
+    if constexpr (HALF) {
+        // projection straight from the packed words; the site norm of the
+        // neighbour and the boundary sign scale the accumulation
+        uint32_t q[12];
+        T nrm;
+        load_spinor_words<SP>(a.in, a.in_norm, a.stride, ncb, q, &nrm);
+        project_half<SP, MU, SG>(q, h0, h1);
+        f = flip ? -nrm : nrm;
     } else {
+        T v[24];
+        load_spinor<SP>(a.in, nullptr, a.stride, ncb, v);
         project<MU, SG>(v, h0, h1);
-    }
-    if constexpr (SP == P_F64 || SP == P_F32) {
         if (flip) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -685,7 +743,10 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
     cpx<T> g0[3], g1[3];
     su3_mul<(DIR < 0), T>(u, h0, g0);
     su3_mul<(DIR < 0), T>(u, h1, g1);
-    reconstruct_add<MU, SG>(acc, g0, g1);
+    if constexpr (HALF)
+        reconstruct_add_scaled<MU, SG>(acc, g0, g1, f);
+    else
+        reconstruct_add<MU, SG>(acc, g0, g1);
 }
 
 // Keeps the compiler from hoisting the loads of later directions above this

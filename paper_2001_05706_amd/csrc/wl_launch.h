@@ -112,6 +112,8 @@ struct HopArgs {
     const int32_t *active;  // per-vector mask (NULL: all active)
     int32_t nblocks;
     int32_t parity;         // output parity
+    int32_t nvec;           // vectors of the set
+    int32_t pad_;
     const void *in;         // field bases (all vectors of the set)
     const float *in_norm;
     void *out;

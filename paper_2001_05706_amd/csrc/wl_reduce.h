@@ -120,6 +120,16 @@ __device__ __forceinline__ void block_reduce_store_n(const RedSpec &r, int pslot
     }
 }
 
+// Per-wave variant (blocks whose waves serve different vectors): the wave's
+// sum goes to its own vector's partial slot; every lane of the wave calls it.
+__device__ __forceinline__ void wave_reduce_store_n(const RedSpec &r, int pslot0, int lblk, const double *mine)
+{
+    for (int k = 0; k < r.nv; ++k) {
+        const double ws = wave_sum(mine[k]);
+        if ((threadIdx.x & 63) == 0) r.partials[(size_t)(pslot0 + lblk) * r.nv + k] = ws;
+    }
+}
+
 // <a, b> = sum conj(a) b over one site (12 complex numbers)
 template <class T> __device__ __forceinline__ void site_cdot(const T a[24], const T b[24], double &re, double &im)
 {

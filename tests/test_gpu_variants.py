@@ -21,8 +21,7 @@ def force(monkeypatch):
     return set_cfg
 
 
-@pytest.mark.parametrize("var", [0, 1, 2, 3, 4, 5])
-@pytest.mark.parametrize("block", [64, 512])
+@pytest.mark.parametrize("var,block", [(v, b) for v in range(6) for b in (64, 512)] + [(6, 256), (6, 512)])
 def test_every_hop_variant_matches_oracle(var, block, force):
     w = need_gpu()
     force(var, block)
@@ -51,3 +50,23 @@ def test_every_hop_variant_solves(var, sloppy, force):
     r = eta - oracle.wilson(L, U, psi, 0.1245)
     tr = np.linalg.norm(r) / np.linalg.norm(eta)
     assert st == w.WL_OK and tr <= 1e-10, (var, sloppy, st, info, tr)
+
+
+@pytest.mark.parametrize("block", [256, 512])
+@pytest.mark.parametrize("sloppy", ["f32", "f16"])
+def test_rhs_block_variant_solves(block, sloppy, force):
+    """variant 6 (the waves of a block serve consecutive right-hand sides): 5
+    right-hand sides, so the last block of 4 or 8 is partly empty"""
+    w = need_gpu()
+    force(6, block)
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1003)
+    eta = li.gaussian_spinor(L, 2003, nrhs=5)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.wilson_cg(g, to_dev(eta), x, 5, 0.1245, 1e-10, 2000, sloppy, 12, 0.1, check=False)
+    psi = from_dev(x, eta.shape)
+    g.close()
+    for r in range(5):
+        tr = np.linalg.norm(eta[r] - oracle.wilson(L, U, psi[r], 0.1245)) / np.linalg.norm(eta[r])
+        assert st == w.WL_OK and tr <= 1e-10, (block, sloppy, r, st, info[r], tr)
