@@ -70,35 +70,50 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
 
     double rv[3] = {0.0, 0.0, 0.0};
     if (valid && cb < sd.Vh) {
+        const double *cf = a.epi.coef + vd.sys * 5;
+        const T c = (T)cf[4];
+        constexpr bool HALF = SP == P_F16 || SP == P_BF16;
         HopSite hs;
         hs.in = (const CH *)a.in + voff;
         hs.in_norm = a.in_norm ? a.in_norm + vd.site_off : nullptr;
         hs.stride = sd.stride;
         hs.gauge = sd.gauge;
         hs.gstride = sd.gstride;
+        hs.scale = HALF ? (float)c : 1.0f;
         T acc[24];
         hop_site<SP, GP, R, DAG, HopVar<SP, VAR>::fence, HopVar<SP, VAR>::nt>(sd, hs, a.parity, cb, acc);
+        // acc = c H psi from here on (half precision: c rode on the accumulation)
+        if constexpr (!HALF) {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) acc[k] *= c;
+        }
 
-        const double *cf = a.epi.coef + vd.sys * 5;
-        const T c = (T)cf[4];
         // clover term of this system at the output site (FP16/BF16 launches use the FP32 copy)
         constexpr int CP = SP == P_F64 ? P_F64 : P_F32;
         const bool clov = CLOV && a.epi.clov != 0 && sd.clov != nullptr;
         T o[24];
         if (a.epi.nx >= 1) {
-            T x[24];
-            load_spinor<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
-                            sd.stride, cb, x);
+            // operand values before their site norm; the norm joins the coefficient
+            T x[24], n0;
+            bool raw = true;
             if constexpr (CLOV) {
-                if (clov && (a.epi.clov & EPI_CLOV_X0))
+                if (clov && (a.epi.clov & EPI_CLOV_X0)) {
+                    load_spinor<SP>((const CH *)a.epi.X[0] + voff,
+                                    a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr, sd.stride, cb, x);
                     clover_apply<CP>(clover_parity<CP>(sd.clov, a.parity, sd.stride), sd.stride, cb, x);
+                    n0 = 1;
+                    raw = false;
+                }
             }
-            const T a0 = (T)cf[0];
+            if (raw)
+                load_spinor_raw<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
+                                    sd.stride, cb, x, &n0);
+            const T s0 = (T)cf[0] * n0;
 #pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = a0 * x[k] + c * acc[k];
+            for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], s0, acc[k]);
         } else {
 #pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = c * acc[k];
+            for (int k = 0; k < 24; ++k) o[k] = acc[k];
         }
         if (a.epi.g5) {
 #pragma unroll
@@ -109,29 +124,32 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
                 clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, o);
         }
         for (int j = 1; j < a.epi.nx; ++j) {
-            T x[24];
-            load_spinor<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
-                            sd.stride, cb, x);
-            const T aj = (T)cf[j];
+            T x[24], nj;
+            load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+                                sd.stride, cb, x, &nj);
+            const T sj = (T)cf[j] * nj;
 #pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] += aj * x[k];
+            for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], sj, o[k]);
         }
         store_spinor<SP>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
         if (a.red.kind != RED_NONE) {
             if (a.red.mode == RM_NORM) {
                 rv[0] = site_norm2(o);
             } else {
-                // the X field was read above; this re-read hits in cache
+                // the X field was read above; this re-read hits in cache.  The
+                // products are linear in x: its site norm scales the site sums.
                 const int j = a.red.mode == RM_DOT_X1 ? 1 : 0;
-                T x[24];
-                load_spinor<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
-                                sd.stride, cb, x);
+                T x[24], nx;
+                load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+                                    sd.stride, cb, x, &nx);
                 if (a.red.mode == RM_DOT_X1) {
                     site_cdot(x, o, rv[0], rv[1]);
                 } else {
                     site_cdot(o, x, rv[0], rv[1]);
                     rv[2] = site_norm2(o);
                 }
+                rv[0] *= (double)nx;
+                rv[1] *= (double)nx;
             }
         }
     }

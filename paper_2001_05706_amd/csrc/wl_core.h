@@ -94,6 +94,15 @@ template <int P> WL_HD float hi16_to_float(uint32_t w)
 {
     return P == P_F16 ? f16_to_float((uint16_t)(w >> 16)) : bf16_to_float((uint16_t)(w >> 16));
 }
+// low (H = 0) or high (H = 1) half of a packed word as FP32
+template <int P, int H> WL_HD float half_part(uint32_t w)
+{
+    if constexpr (P == P_F16) return H ? hi16_to_float<P>(w) : lo16_to_float<P>(w);
+    union { uint32_t u; float f; } c;
+    c.u = H ? (w & 0xFFFF0000u) : (w << 16);
+    return c.f;
+}
+
 template <int P> WL_HD uint32_t pack2(float lo, float hi)
 {
     uint32_t a = P == P_F16 ? float_to_f16(lo) : float_to_bf16(lo);
@@ -235,6 +244,30 @@ WL_HD void load_spinor_words(const void *base, const float *norm, int stride, in
         q[4 * c + 1] = w.y;
         q[4 * c + 2] = w.z;
         q[4 * c + 3] = w.w;
+    }
+}
+
+// The 24 reals of a site before its half-precision norm is applied, and that
+// norm in *nrm (FP64/FP32: the values themselves and 1).  A caller folds the
+// norm into a per-site coefficient; FP16 values then enter mixed-precision fmas
+// directly.
+template <int P>
+WL_HD void load_spinor_raw(const void *base, const float *norm, int stride, int cb,
+                           typename SpinorFmt<P>::real v[24], typename SpinorFmt<P>::real *nrm)
+{
+    if constexpr (P == P_F64 || P == P_F32) {
+        load_spinor<P>(base, norm, stride, cb, v);
+        *nrm = 1;
+    } else {
+        uint32_t q[12];
+        float n;
+        load_spinor_words<P>(base, norm, stride, cb, q, &n);
+        *nrm = n;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            v[2 * k] = half_part<P, 0>(q[k]);
+            v[2 * k + 1] = half_part<P, 1>(q[k]);
+        }
     }
 }
 
@@ -510,14 +543,6 @@ WL_HD void project(const T v[24], cpx<T> h0[3], cpx<T> h1[3])
 // conversions: FP16 through one mixed-precision fma (a * 1 + (+-b), each half
 // selected in place), BF16 by moving the half to the top of an FP32 word.
 
-template <int P, int H> WL_HD float half_part(uint32_t w)
-{
-    if constexpr (P == P_F16) return H ? hi16_to_float<P>(w) : lo16_to_float<P>(w);
-    union { uint32_t u; float f; } c;
-    c.u = H ? (w & 0xFFFF0000u) : (w << 16);
-    return c.f;
-}
-
 template <int P, int HA, int HB, bool NEG> WL_HD float half_sum(uint32_t a, uint32_t b)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -685,6 +710,7 @@ struct HopSite {
     int stride;           // chunk stride of spinor vectors
     const void *gauge;    // packed links of the system: [parity][mu][chunk][gstride]
     int gstride;
+    float scale = 1.0f;   // FP16/BF16: factor folded into the accumulation (unused otherwise)
 };
 
 template <int SP, int GP, int R, int MU, int DIR, bool DAG, bool NT, class T>
@@ -719,7 +745,7 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
         T nrm;
         load_spinor_words<SP>(a.in, a.in_norm, a.stride, ncb, q, &nrm);
         project_half<SP, MU, SG>(q, h0, h1);
-        f = flip ? -nrm : nrm;
+        f = (flip ? -nrm : nrm) * (T)a.scale;
     } else {
         T v[24];
         load_spinor<SP>(a.in, nullptr, a.stride, ncb, v);
