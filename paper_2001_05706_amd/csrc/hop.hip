@@ -131,7 +131,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
 #pragma unroll
             for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], sj, o[k]);
         }
-        store_spinor<SP>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
+        store_spinor<SP, true>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
         if (a.red.kind != RED_NONE) {
             if (a.red.mode == RM_NORM) {
                 rv[0] = site_norm2(o);

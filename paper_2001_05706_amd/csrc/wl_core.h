@@ -152,12 +152,38 @@ typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef float nt_f2 __attribute__((ext_vector_type(2)));
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef uint32_t nt_u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
 
 #if defined(__HIP_DEVICE_COMPILE__)
 #define WL_NT_LOAD(VT, p) __builtin_nontemporal_load((const VT *)(p))
+#define WL_NT_STORE(VT, v, p) __builtin_nontemporal_store((v), (VT *)(p))
 #else
 #define WL_NT_LOAD(VT, p) (*(const VT *)(p))
+#define WL_NT_STORE(VT, v, p) (*(VT *)(p) = (v))
 #endif
+
+// stores of written-once data (a kernel's output field), plain or with the
+// non-temporal hint
+template <bool NT> WL_HD void st_out(double2 *p, double2 v)
+{
+    if constexpr (NT) WL_NT_STORE(nt_d2, (nt_d2{v.x, v.y}), p);
+    else *p = v;
+}
+template <bool NT> WL_HD void st_out(float4 *p, float4 v)
+{
+    if constexpr (NT) WL_NT_STORE(nt_f4, (nt_f4{v.x, v.y, v.z, v.w}), p);
+    else *p = v;
+}
+template <bool NT> WL_HD void st_out(uint4 *p, uint4 v)
+{
+    if constexpr (NT) WL_NT_STORE(nt_u4, (nt_u4{v.x, v.y, v.z, v.w}), p);
+    else *p = v;
+}
+template <bool NT> WL_HD void st_out(float *p, float v)
+{
+    if constexpr (NT) WL_NT_STORE(float, v, p);
+    else *p = v;
+}
 
 WL_HD double2 ld_stream(const double2 *p)
 {
@@ -271,31 +297,31 @@ WL_HD void load_spinor_raw(const void *base, const float *norm, int stride, int 
     }
 }
 
-template <int P>
+template <int P, bool NT = false>
 WL_HD void store_spinor(void *base, float *norm, int stride, int cb, const typename SpinorFmt<P>::real v[24])
 {
     using F = SpinorFmt<P>;
     typename F::chunk *b = (typename F::chunk *)base;
     if constexpr (P == P_F64) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) *row_elem<double2>(b, c, stride, cb) = double2{v[2 * c], v[2 * c + 1]};
+        for (int c = 0; c < 12; ++c) st_out<NT>(row_elem<double2>(b, c, stride, cb), double2{v[2 * c], v[2 * c + 1]});
     } else if constexpr (P == P_F32) {
 #pragma unroll
         for (int c = 0; c < 6; ++c)
-            *row_elem<float4>(b, c, stride, cb) = float4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+            st_out<NT>(row_elem<float4>(b, c, stride, cb), float4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]});
     } else {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
         // a zero site stores zeros and a zero norm (point sources are zero almost everywhere)
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        *row_elem<float>(norm, 0, 0, cb) = m;
+        st_out<NT>(row_elem<float>(norm, 0, 0, cb), m);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             uint32_t q[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) q[k] = pack2<P>(v[8 * c + 2 * k] * inv, v[8 * c + 2 * k + 1] * inv);
-            *row_elem<uint4>(b, c, stride, cb) = uint4{q[0], q[1], q[2], q[3]};
+            st_out<NT>(row_elem<uint4>(b, c, stride, cb), uint4{q[0], q[1], q[2], q[3]});
         }
     }
 }
