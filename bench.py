@@ -66,9 +66,10 @@ def log(msg):
 
 def cg_iteration_bytes(w, prec, recon, vh):
     """Algorithmic bytes of one CGNR iteration per the library's byte model:
-    4 hops (+2 epilogue reads), x/r update (6 passes), p = s + beta p (3)."""
+    4 hops (+2 epilogue reads), r update (3 passes), x += alpha p with
+    p = s + beta p (5)."""
     site = {"f64": 192, "f32": 96, "f16": 52, "bf16": 52}[prec]
-    return vh * (4 * w.wl_hop_bytes_per_site(prec, recon, 1) + 2 * site + 6 * site + 3 * site)
+    return vh * (4 * w.wl_hop_bytes_per_site(prec, recon, 1) + 2 * site + 3 * site + 5 * site)
 
 
 def _guard(fn):

@@ -76,6 +76,48 @@ __global__ __launch_bounds__(256) void k_xpay(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
+// CGNR with the solution update folded into the direction update: the
+// residual step alone here, x += alpha p with p = s + beta p below
+template <int P>
+__global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    double nrm = 0.0;
+    if (live) {
+        const T al = (T)a.s0[bm.v];
+        T r[24], q[24];
+        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, q);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) r[k] -= al * q[k];
+        store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+        nrm = site_norm2(r);
+    }
+    if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
+{
+    using T = typename SpinorFmt<P>::real;
+    WL_BLAS_PROLOGUE
+    if (!live) return;
+    const T be = (T)a.s0[bm.v];
+    const T al = (T)a.sc[SC_ALPHA * a.nvec + bm.v];
+    T p[24], s[24], x[24];
+    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
+    load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        x[k] += al * p[k];
+        p[k] = s[k] + be * p[k];
+    }
+    store_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
+    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_accum(BlasArgs a)
 {
@@ -378,6 +420,8 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
     case BL_CAXPY: hipLaunchKernelGGL((k_caxpy<P, false>), g, b, 0, s, a); break;
     case BL_CAXPY_G5: hipLaunchKernelGGL((k_caxpy<P, true>), g, b, 0, s, a); break;
     case BL_ROT: hipLaunchKernelGGL(k_rot<P>, g, b, 0, s, a); break;
+    case BL_R_UPDATE: hipLaunchKernelGGL(k_r_update<P>, g, b, 0, s, a); break;
+    case BL_XPAY_X: hipLaunchKernelGGL(k_xpay_x<P>, g, b, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -171,15 +171,17 @@ struct Cg {
             WL_TRY(blas(S, BL_BICG_XR, sloppy, fx, 6, nullptr, red_spec(S, RED_BICG_RHO, hist_row, 3), s));
             return WL_OK;
         }
+        // q = M p, alpha = gamma / |q|^2;  r -= alpha q;  s = M^dagger r, beta;
+        // then x += alpha p and p = s + beta p in one pass over p
         WL_TRY(apply_M(sloppy, recon, false, q, p, tl, red_spec(S, RED_ALPHA, nullptr)));
-        Field f[4] = {xl, p, rl, q};
+        Field f[2] = {rl, q};
         RedSpec rr = red_spec(S, RED_STORE, hist_row);
         rr.partials = S.hist_partials + (size_t)j * S.max_pslots;
         rr.defer = 1;
-        WL_TRY(blas(S, BL_CG_UPDATE, sloppy, f, 4, S.scal(SC_ALPHA), rr, s));
+        WL_TRY(blas(S, BL_R_UPDATE, sloppy, f, 2, S.scal(SC_ALPHA), rr, s));
         WL_TRY(apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_BETA, nullptr)));
-        Field g[2] = {p, sv};
-        WL_TRY(blas(S, BL_XPAY, sloppy, g, 2, S.scal(SC_BETA), no_red(), s));
+        Field g[3] = {p, sv, xl};
+        WL_TRY(blas(S, BL_XPAY_X, sloppy, g, 3, S.scal(SC_BETA), no_red(), s));
         return WL_OK;
     }
 
@@ -188,7 +190,7 @@ struct Cg {
         if (method == M_BICGSTAB)  // 4 hops (+3 epilogue reads), p (4), s (3), x/r (7)
             return 4 * hop_bytes(S, sloppy, recon, true) + blas_bytes(S, sloppy, 3 + 4 + 3 + 7, true);
         return 4 * hop_bytes(S, sloppy, recon, true) + 2 * blas_bytes(S, sloppy, 1, true) +
-               blas_bytes(S, sloppy, 6, true) + blas_bytes(S, sloppy, 3, true);
+               blas_bytes(S, sloppy, 3, true) + blas_bytes(S, sloppy, 5, true);
     }
 
     // After the FP64 residual rh is fresh: continue (cont) or restart (restart)

@@ -739,7 +739,7 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.red = red;
     a.parity = parity;
     a.bcast = bcast;
-    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2, 2, 3, 3, 0};
+    static const int passes[] = {6, 3, 0, 1, 1, 2, 1, 2, 4, 3, 7, 2, 2, 2, 3, 3, 0, 3, 5};
     if (op == BL_CLOV_INV) g_bytes_acc += clover_bytes(S, prec, use_active);
     if (op == BL_ROT) g_bytes_acc += blas_bytes(S, prec, S.nvec + 1, use_active);
     if (op == BL_ACCUM)

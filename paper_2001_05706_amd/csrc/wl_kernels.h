@@ -63,6 +63,9 @@ enum BlasOp {
     BL_CAXPY = 14,     // y += z x, z = (s0[2v], s0[2v+1])                                  f = {y, x}
     BL_CAXPY_G5 = 15,  // y += z g5 x                                                       f = {y, x}
     BL_ROT = 16,       // y_v = sum_j T[j + nvec v] x_j, T complex (s0)                      f = {y, x}
+    // CGNR iteration with the solution update moved into the direction update:
+    BL_R_UPDATE = 17,  // r -= alpha q; |r|^2                                               f = {r, q},    s0 = alpha
+    BL_XPAY_X = 18,    // x += alpha p; p = s + beta p (alpha from its slot)                  f = {p, s, x}, s0 = beta
 };
 hipError_t launch_blas(int op, int prec, const BlasArgs &a, int block, hipStream_t s);
 // fixed-order sum of each active vector's block partials and the reduction's finishing step
