@@ -429,18 +429,36 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
 
 // One block per vector: fixed-order sum of the vector's partials, then the
 // finishing step (scalar update) of the reduction kind.
+template <int NV>
 __global__ __launch_bounds__(1024) void k_red_finalize(RedSpec r, const VecDesc *vec, const int32_t *active)
 {
     const int v = blockIdx.x;
     if (active && !active[v]) return;
+    RedIn in;
+    if (threadIdx.x == 0) in = red_prefetch(r, v);
     const VecDesc vd = vec[v];
+    const double *p = r.partials + (size_t)vd.pslot0 * NV;
+    const int bd = (int)blockDim.x;
     double tot[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < r.nv; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < vd.nblk; i += blockDim.x) s += r.partials[(size_t)(vd.pslot0 + i) * r.nv + k];
-        tot[k] = block_sum(s);
+    // four partials per step, all loaded before any is added (their latencies
+    // overlap), then the tail; the order of the additions is fixed
+    int i = threadIdx.x;
+    for (; i + 3 * bd < vd.nblk; i += 4 * bd) {
+        double w[4][NV];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) w[u][k] = p[(size_t)(i + u * bd) * NV + k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) tot[k] += w[u][k];
     }
-    if (threadIdx.x == 0) red_finalize(r, v, tot);
+    for (; i < vd.nblk; i += bd)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) tot[k] += p[(size_t)i * NV + k];
+    block_sum_n(tot, NV);
+    if (threadIdx.x == 0) red_finalize(r, v, tot, in);
 }
 
 // Deferred |r|^2 of k iterations: block (v, j) sums row j of the per-iteration
@@ -470,7 +488,12 @@ hipError_t launch_hist_finalize(const double *partials, size_t row, const VecDes
 
 hipError_t launch_red_finalize(const RedSpec &r, const VecDesc *vec, const int32_t *active, int nvec, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_red_finalize, dim3(nvec), dim3(1024), 0, s, r, vec, active);
+    switch (r.nv) {
+    case 1: hipLaunchKernelGGL(k_red_finalize<1>, dim3(nvec), dim3(1024), 0, s, r, vec, active); break;
+    case 2: hipLaunchKernelGGL(k_red_finalize<2>, dim3(nvec), dim3(1024), 0, s, r, vec, active); break;
+    case 3: hipLaunchKernelGGL(k_red_finalize<3>, dim3(nvec), dim3(1024), 0, s, r, vec, active); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -35,7 +35,51 @@ __device__ __forceinline__ double block_sum(double v)
     return r;
 }
 
-__device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const double *s)
+// Sums over the block of nv <= 3 values per thread, valid in thread 0: one
+// pass of LDS traffic for all of them.
+__device__ __forceinline__ void block_sum_n(double *v, int nv)
+{
+    __shared__ double lds[3][16];
+    __syncthreads();  // lds may still be read by a previous call
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int k = 0; k < nv; ++k) {
+        v[k] = wave_sum(v[k]);
+        if (l == 0) lds[k][w] = v[k];
+    }
+    __syncthreads();
+    if (w == 0)
+        for (int k = 0; k < nv; ++k) v[k] = wave_sum(l < (int)(blockDim.x >> 6) ? lds[k][l] : 0.0);
+}
+
+// The values the finishing step of a reduction reads besides the sums
+// (loaded before the sums are complete, so that their latency overlaps).
+struct RedIn {
+    double a = 0.0, b = 0.0;
+};
+
+__device__ __forceinline__ RedIn red_prefetch(const RedSpec &r, int v)
+{
+    RedIn in;
+    const double *sc = r.sc;
+    const int n = r.nvec;
+    switch (r.kind) {
+    case RED_ALPHA:
+    case RED_BETA: in.a = sc[SC_GAM * n + v]; break;
+    case RED_ACCUM: in.a = r.dst[v]; break;
+    case RED_BICG_ALPHA:
+        in.a = sc[SC_RHO_RE * n + v];
+        in.b = sc[SC_RHO_IM * n + v];
+        break;
+    case RED_CACCUM:
+        in.a = r.dst[2 * v];
+        in.b = r.dst[2 * v + 1];
+        break;
+    default: break;
+    }
+    return in;
+}
+
+__device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const double *s, const RedIn &in)
 {
     bool finite = true;
     for (int k = 0; k < r.nv; ++k) finite = finite && isfinite(s[k]);
@@ -44,15 +88,15 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const doub
 #define WL_SC(slot) sc[(slot) * n + v]
     switch (r.kind) {
     case RED_STORE: r.dst[v] = s[0]; break;
-    case RED_ALPHA: WL_SC(SC_ALPHA) = s[0] > 0.0 ? WL_SC(SC_GAM) / s[0] : 0.0; break;
+    case RED_ALPHA: WL_SC(SC_ALPHA) = s[0] > 0.0 ? in.a / s[0] : 0.0; break;
     case RED_BETA: {
-        const double g = WL_SC(SC_GAM);
+        const double g = in.a;
         WL_SC(SC_BETA) = g > 0.0 ? s[0] / g : 0.0;
         WL_SC(SC_GAM) = s[0];
         break;
     }
     case RED_GAMMA: WL_SC(SC_GAM) = s[0]; break;
-    case RED_ACCUM: r.dst[v] += s[0]; break;
+    case RED_ACCUM: r.dst[v] = in.a + s[0]; break;
     case RED_CDOT_RHO:
         WL_SC(SC_RHO_RE) = s[0];
         WL_SC(SC_RHO_IM) = s[1];
@@ -60,7 +104,7 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const doub
     case RED_BICG_ALPHA: {
         // alpha = rho / d, a zero d is a breakdown: reported as non-finite
         const double dr = s[0], di = s[1], d2 = dr * dr + di * di;
-        const double rr = WL_SC(SC_RHO_RE), ri = WL_SC(SC_RHO_IM);
+        const double rr = in.a, ri = in.b;
         if (!(d2 > 0.0)) finite = false;
         WL_SC(SC_AL_RE) = d2 > 0.0 ? (rr * dr + ri * di) / d2 : 0.0;
         WL_SC(SC_AL_IM) = d2 > 0.0 ? (ri * dr - rr * di) / d2 : 0.0;
@@ -90,8 +134,8 @@ __device__ __forceinline__ void red_finalize(const RedSpec &r, int v, const doub
         r.dst[2 * v + 1] = s[1];
         break;
     case RED_CACCUM:
-        r.dst[2 * v] += s[0];
-        r.dst[2 * v + 1] += s[1];
+        r.dst[2 * v] = in.a + s[0];
+        r.dst[2 * v + 1] = in.b + s[1];
         break;
     default: break;
     }
