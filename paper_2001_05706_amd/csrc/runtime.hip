@@ -154,25 +154,33 @@ int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream
         (void)hipEventDestroy(e0);
         return fallback;
     }
+    // two sweeps over the candidates, each candidate scored by its faster sweep
+    // (a single short sweep picks among near-equal candidates by noise)
+    std::vector<float> score(cands.size(), 1e30f);
+    for (int sweep = 0; sweep < 2; ++sweep)
+        for (size_t i = 0; i < cands.size(); ++i) {
+            const int B = cands[i];
+            if (sweep > 0 && score[i] >= 1e30f) continue;  // failed in the first sweep
+            if (run(B) != hipSuccess) {  // warm-up; a failed launch rules the candidate out
+                (void)hipGetLastError();
+                continue;
+            }
+            (void)hipEventRecord(e0, s);
+            const int reps = 3;
+            bool ok = true;
+            for (int r = 0; r < reps; ++r) ok = ok && run(B) == hipSuccess;
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) score[i] = std::min(score[i], ms);
+        }
     int best = fallback;
     float best_ms = 1e30f;
-    for (int B : cands) {
-        if (run(B) != hipSuccess) {  // warm-up; a failed launch rules the candidate out
-            (void)hipGetLastError();
-            continue;
+    for (size_t i = 0; i < cands.size(); ++i)
+        if (score[i] < best_ms) {
+            best_ms = score[i];
+            best = cands[i];
         }
-        (void)hipEventRecord(e0, s);
-        const int reps = 3;
-        bool ok = true;
-        for (int r = 0; r < reps; ++r) ok = ok && run(B) == hipSuccess;
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-            best_ms = ms;
-            best = B;
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (getenv("WL_DEBUG")) fprintf(stderr, "[wl tune] %s -> %d (%.4f ms / 3 launches)\n", key.c_str(), best, best_ms);
