@@ -5,9 +5,9 @@
 // spinor is spin-projected to two components (12 flop), both are multiplied
 // by the link (2 x 66 flop) rebuilt from 12 reals when recon = 12, and the
 // result is spin-reconstructed into the accumulator (24 flop): 1320 flop per
-// site.  Links are read with non-temporal loads (each is used once per hop);
-// neighbour spinors are shared by up to 8 output sites through L2, which the
-// XCD-aware block order keeps on one die.
+// site.  Each link is used once per hop and right-hand side; neighbour
+// spinors are shared by up to 8 output sites through L2, which the XCD-aware
+// block order keeps on one die.
 #include <hip/hip_ext.h>
 
 #include "wl_reduce.h"
@@ -28,26 +28,131 @@ namespace wl {
 //   6: as 3, but the waves of a block serve consecutive right-hand sides of one
 //      system on the same 64 sites, so the links they share hit in the CU's L1
 //      (multi-RHS sets; launched on the layouts of `ExecSet::layout(-G)`)
+//   7: each thread serves two right-hand sides of one system at its site: the
+//      neighbour index and each link (with its recon-12 row) are formed once
+//      for both; one direction in flight, 3 waves (multi-RHS sets; pair layouts)
 // Variants 4 and 5 exist for FP16/BF16 storage only (FP32 and FP64 operands of
 // four directions do not fit the registers); for those they repeat variant 3.
 template <int SP, int VAR> struct HopVar {
     static constexpr bool half = SP == P_F16 || SP == P_BF16;
-    static constexpr int fence = VAR == 0 || VAR == 3 || VAR == 6 ? 2 : (VAR >= 4 ? (half ? 4 : 2) : 1);
+    static constexpr int fence = VAR == 0 || VAR == 3 || VAR == 6 ? 2 : (VAR == 4 || VAR == 5 ? (half ? 4 : 2) : 1);
     static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR >= 3 ? 2 : 3)
-                                             : (VAR == 0 || VAR == 3 || VAR == 4 || VAR == 6 ? 4 : VAR == 2 ? 6 : 5);
+                                             : (VAR == 7 ? 3 : VAR == 0 || VAR == 3 || VAR == 4 || VAR == 6 ? 4
+                                                                 : VAR == 2 ? 6 : 5);
     static constexpr bool nt = VAR < 3;
     static constexpr bool rhs_waves = VAR == 6;
+    static constexpr bool rhs_pairs = VAR == 7;
 };
-constexpr int kHopVariants = 7;
+constexpr int kHopVariants = 8;
+
+// Everything after the hopping sum at one output site of one vector: the
+// linear-combination epilogue, the store, and the site's reduction values.
+// acc holds H psi (FP16/BF16: already multiplied by the system's c).
+template <int SP, bool CLOV>
+__device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd, const SysDesc &sd, int cb,
+                                             typename SpinorFmt<SP>::real acc[24], double rv[3])
+{
+    using T = typename SpinorFmt<SP>::real;
+    using CH = typename SpinorFmt<SP>::chunk;
+    constexpr int NC = SpinorFmt<SP>::nchunk;
+    const size_t voff = (size_t)vd.site_off * NC;
+    const double *cf = a.epi.coef + vd.sys * 5;
+    constexpr bool HALF = SP == P_F16 || SP == P_BF16;
+    // acc = c H psi from here on (half precision: c rode on the accumulation)
+    if constexpr (!HALF) {
+        const T c = (T)cf[4];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] *= c;
+    }
+
+    // clover term of this system at the output site (FP16/BF16 launches use the FP32 copy)
+    constexpr int CP = SP == P_F64 ? P_F64 : P_F32;
+    const bool clov = CLOV && a.epi.clov != 0 && sd.clov != nullptr;
+    T o[24];
+    if (a.epi.nx >= 1) {
+        // operand values before their site norm; the norm joins the coefficient
+        T x[24], n0;
+        bool raw = true;
+        if constexpr (CLOV) {
+            if (clov && (a.epi.clov & EPI_CLOV_X0)) {
+                load_spinor<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
+                                sd.stride, cb, x);
+                clover_apply<CP>(clover_parity<CP>(sd.clov, a.parity, sd.stride), sd.stride, cb, x);
+                n0 = 1;
+                raw = false;
+            }
+        }
+        if (raw)
+            load_spinor_raw<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
+                                sd.stride, cb, x, &n0);
+        const T s0 = (T)cf[0] * n0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], s0, acc[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] = acc[k];
+    }
+    if (a.epi.g5) {
+#pragma unroll
+        for (int k = 12; k < 24; ++k) o[k] = -o[k];
+    }
+    if constexpr (CLOV) {
+        if (clov && (a.epi.clov & EPI_CLOV_INV))
+            clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, o);
+    }
+    for (int j = 1; j < a.epi.nx; ++j) {
+        T x[24], nj;
+        load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+                            sd.stride, cb, x, &nj);
+        const T sj = (T)cf[j] * nj;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], sj, o[k]);
+    }
+    store_spinor<SP, true>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
+    if (a.red.kind != RED_NONE) {
+        if (a.red.mode == RM_NORM) {
+            rv[0] = site_norm2(o);
+        } else {
+            // the X field was read above; this re-read hits in cache.  The
+            // products are linear in x: its site norm scales the site sums.
+            const int j = a.red.mode == RM_DOT_X1 ? 1 : 0;
+            T x[24], nx;
+            load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+                                sd.stride, cb, x, &nx);
+            if (a.red.mode == RM_DOT_X1) {
+                site_cdot(x, o, rv[0], rv[1]);
+            } else {
+                site_cdot(o, x, rv[0], rv[1]);
+                rv[2] = site_norm2(o);
+            }
+            rv[0] *= (double)nx;
+            rv[1] *= (double)nx;
+        }
+    }
+}
+
+template <int SP>
+__device__ __forceinline__ HopSite hop_input(const HopArgs &a, const VecDesc &vd, const SysDesc &sd)
+{
+    using CH = typename SpinorFmt<SP>::chunk;
+    constexpr bool HALF = SP == P_F16 || SP == P_BF16;
+    HopSite hs;
+    hs.in = (const CH *)a.in + (size_t)vd.site_off * SpinorFmt<SP>::nchunk;
+    hs.in_norm = a.in_norm ? a.in_norm + vd.site_off : nullptr;
+    hs.stride = sd.stride;
+    hs.gauge = sd.gauge;
+    hs.gstride = sd.gstride;
+    hs.scale = HALF ? (float)a.epi.coef[vd.sys * 5 + 4] : 1.0f;
+    return hs;
+}
 
 template <int SP, int GP, int R, bool DAG, int VAR, bool CLOV>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves))) void k_hop(HopArgs a)
 {
     using T = typename SpinorFmt<SP>::real;
-    using CH = typename SpinorFmt<SP>::chunk;
-    constexpr int NC = SpinorFmt<SP>::nchunk;
 
     constexpr bool RW = HopVar<SP, VAR>::rhs_waves;
+    constexpr bool PAIR = HopVar<SP, VAR>::rhs_pairs;
     const int lb = xcd_remap(blockIdx.x, a.nblocks);
     const BlkMap bm = a.map[lb];
     int v = bm.v, cb;
@@ -59,6 +164,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
         v = bm.v + w;
         valid = v < a.nvec && a.vec[v].sys == a.vec[bm.v].sys && (!a.active || a.active[v]);
         cb = bm.lblk * 64 + ((int)threadIdx.x & 63);
+    } else if constexpr (PAIR) {
+        cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
     } else {
         if (a.active && !a.active[bm.v]) return;
         cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
@@ -66,97 +173,40 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     const unsigned long long t_start = a.stamps ? (unsigned long long)wall_clock64() : 0ull;
     const VecDesc vd = a.vec[valid ? v : bm.v];
     const SysDesc sd = a.sys[vd.sys];
-    const size_t voff = (size_t)vd.site_off * NC;
 
-    double rv[3] = {0.0, 0.0, 0.0};
-    if (valid && cb < sd.Vh) {
-        const double *cf = a.epi.coef + vd.sys * 5;
-        const T c = (T)cf[4];
-        constexpr bool HALF = SP == P_F16 || SP == P_BF16;
-        HopSite hs;
-        hs.in = (const CH *)a.in + voff;
-        hs.in_norm = a.in_norm ? a.in_norm + vd.site_off : nullptr;
-        hs.stride = sd.stride;
-        hs.gauge = sd.gauge;
-        hs.gstride = sd.gstride;
-        hs.scale = HALF ? (float)c : 1.0f;
-        T acc[24];
-        hop_site<SP, GP, R, DAG, HopVar<SP, VAR>::fence, HopVar<SP, VAR>::nt>(sd, hs, a.parity, cb, acc);
-        // acc = c H psi from here on (half precision: c rode on the accumulation)
-        if constexpr (!HALF) {
-#pragma unroll
-            for (int k = 0; k < 24; ++k) acc[k] *= c;
+    if constexpr (PAIR) {
+        // vectors bm.v and bm.v + 1 (when that is a further rhs of the same
+        // system); an absent second vector is computed from the first and not stored
+        const int v1 = bm.v + 1;
+        const bool has1 = v1 < a.nvec && a.vec[v1].sys == vd.sys;
+        const bool live0 = !a.active || a.active[bm.v];
+        const bool live1 = has1 && (!a.active || a.active[v1]);
+        if (!live0 && !live1) return;
+        const VecDesc vd1 = a.vec[has1 ? v1 : bm.v];
+        double rv0[3] = {0.0, 0.0, 0.0}, rv1[3] = {0.0, 0.0, 0.0};
+        if (cb < sd.Vh) {
+            const HopSite hs0 = hop_input<SP>(a, vd, sd), hs1 = hop_input<SP>(a, vd1, sd);
+            T acc0[24], acc1[24];
+            hop_site2<SP, GP, R, DAG, HopVar<SP, VAR>::nt>(sd, hs0, hs1, a.parity, cb, acc0, acc1);
+            if (live0) hop_epilogue<SP, CLOV>(a, vd, sd, cb, acc0, rv0);
+            if (live1) hop_epilogue<SP, CLOV>(a, vd1, sd, cb, acc1, rv1);
         }
-
-        // clover term of this system at the output site (FP16/BF16 launches use the FP32 copy)
-        constexpr int CP = SP == P_F64 ? P_F64 : P_F32;
-        const bool clov = CLOV && a.epi.clov != 0 && sd.clov != nullptr;
-        T o[24];
-        if (a.epi.nx >= 1) {
-            // operand values before their site norm; the norm joins the coefficient
-            T x[24], n0;
-            bool raw = true;
-            if constexpr (CLOV) {
-                if (clov && (a.epi.clov & EPI_CLOV_X0)) {
-                    load_spinor<SP>((const CH *)a.epi.X[0] + voff,
-                                    a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr, sd.stride, cb, x);
-                    clover_apply<CP>(clover_parity<CP>(sd.clov, a.parity, sd.stride), sd.stride, cb, x);
-                    n0 = 1;
-                    raw = false;
-                }
-            }
-            if (raw)
-                load_spinor_raw<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
-                                    sd.stride, cb, x, &n0);
-            const T s0 = (T)cf[0] * n0;
-#pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], s0, acc[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = acc[k];
-        }
-        if (a.epi.g5) {
-#pragma unroll
-            for (int k = 12; k < 24; ++k) o[k] = -o[k];
-        }
-        if constexpr (CLOV) {
-            if (clov && (a.epi.clov & EPI_CLOV_INV))
-                clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, o);
-        }
-        for (int j = 1; j < a.epi.nx; ++j) {
-            T x[24], nj;
-            load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
-                                sd.stride, cb, x, &nj);
-            const T sj = (T)cf[j] * nj;
-#pragma unroll
-            for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], sj, o[k]);
-        }
-        store_spinor<SP, true>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
-        if (a.red.kind != RED_NONE) {
-            if (a.red.mode == RM_NORM) {
-                rv[0] = site_norm2(o);
-            } else {
-                // the X field was read above; this re-read hits in cache.  The
-                // products are linear in x: its site norm scales the site sums.
-                const int j = a.red.mode == RM_DOT_X1 ? 1 : 0;
-                T x[24], nx;
-                load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
-                                    sd.stride, cb, x, &nx);
-                if (a.red.mode == RM_DOT_X1) {
-                    site_cdot(x, o, rv[0], rv[1]);
-                } else {
-                    site_cdot(o, x, rv[0], rv[1]);
-                    rv[2] = site_norm2(o);
-                }
-                rv[0] *= (double)nx;
-                rv[1] *= (double)nx;
-            }
-        }
-    }
-    if constexpr (RW) {
-        if (a.red.kind != RED_NONE && valid) wave_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+        // live0 and live1 are uniform over the block
+        if (a.red.kind != RED_NONE && live0) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv0);
+        if (a.red.kind != RED_NONE && live1) block_reduce_store_n(a.red, vd1.pslot0, bm.lblk, rv1);
     } else {
-        if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+        double rv[3] = {0.0, 0.0, 0.0};
+        if (valid && cb < sd.Vh) {
+            const HopSite hs = hop_input<SP>(a, vd, sd);
+            T acc[24];
+            hop_site<SP, GP, R, DAG, HopVar<SP, VAR>::fence, HopVar<SP, VAR>::nt>(sd, hs, a.parity, cb, acc);
+            hop_epilogue<SP, CLOV>(a, vd, sd, cb, acc, rv);
+        }
+        if constexpr (RW) {
+            if (a.red.kind != RED_NONE && valid) wave_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+        } else {
+            if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+        }
     }
     if (a.stamps) {
         // the block's work ends when its last wave ends
@@ -208,6 +258,7 @@ static hipError_t launch_hop_t(int var, bool dag, bool clov, const HopArgs &a, i
     case 4: return launch_hop_v<SP, GP, R, 4>(dag, clov, a, block, s, e0, e1);
     case 5: return launch_hop_v<SP, GP, R, 5>(dag, clov, a, block, s, e0, e1);
     case 6: return launch_hop_v<SP, GP, R, 6>(dag, clov, a, block, s, e0, e1);
+    case 7: return launch_hop_v<SP, GP, R, 7>(dag, clov, a, block, s, e0, e1);
     }
     return hipErrorInvalidValue;
 }

@@ -401,8 +401,10 @@ wl_status ExecSet::layout(int B, const Layout **out)
     }
     Layout L;
     L.B = B;
-    // B < 0: blocks of -B right-hand sides (one wave each) on 64 sites
-    const int G = B < 0 ? -B : 1, sites = B < 0 ? 64 : B;
+    // B < 0: blocks of -B right-hand sides (one wave each) on 64 sites;
+    // B >= kPairLayout: blocks of B - kPairLayout sites of two right-hand sides
+    const bool pairs = B >= kPairLayout;
+    const int G = B < 0 ? -B : (pairs ? 2 : 1), sites = B < 0 ? 64 : (pairs ? B - kPairLayout : B);
     std::vector<VecDesc> hv = vec;
     std::vector<BlkMap> map;
     int ps = 0, vbase = 0;
@@ -610,17 +612,19 @@ std::vector<int> hop_candidates(int prec)
             for (int b : {256, 512}) c.push_back(v * 1024 + b);  // 4 or 8 right-hand sides per block
             continue;
         }
+        if (v == 7 && prec == P_F64) continue;  // two FP64 accumulators do not fit the registers
         for (int b : {64, 128, 256, 512}) c.push_back(v * 1024 + b);
     }
     return c;
 }
 
 // the block layout a hop launch configuration runs on: variant 6 blocks hold
-// B / 64 right-hand sides of 64 sites each
+// B / 64 right-hand sides of 64 sites each, variant 7 blocks B sites of two
+// right-hand sides
 static wl_status hop_layout(ExecSet &S, int cfg, const Layout **L)
 {
     const int var = cfg / 1024, B = cfg % 1024;
-    return S.layout(var == 6 ? -(B / 64) : B, L);
+    return S.layout(var == 6 ? -(B / 64) : var == 7 ? kPairLayout + B : B, L);
 }
 
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
@@ -660,8 +664,8 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
                     cands.end());
     int max_nrhs = 0;
     for (auto &e : S.systems) max_nrhs = std::max(max_nrhs, e.nrhs);
-    if (max_nrhs < 2)  // right-hand-side blocks need several right-hand sides
-        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 == 6; }), cands.end());
+    if (max_nrhs < 2)  // right-hand-side blocks and pairs need several right-hand sides
+        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 >= 6; }), cands.end());
     if (cands.empty()) cands = hop_candidates(prec);
     const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;

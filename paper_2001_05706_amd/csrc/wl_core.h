@@ -739,12 +739,13 @@ struct HopSite {
     float scale = 1.0f;   // FP16/BF16: factor folded into the accumulation (unused otherwise)
 };
 
-template <int SP, int GP, int R, int MU, int DIR, bool DAG, bool NT, class T>
-WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s, int cb, T acc[24])
+// Neighbour of site s in direction +-mu: its checkerboard index, and whether
+// the hop wraps the antiperiodic time boundary.
+template <int MU, int DIR>
+WL_HD int neighbour(const SysDesc &d, const Site &s, bool &flip)
 {
-    // neighbour coordinates and boundary factor
     int nx = s.x, ny = s.y, nz = s.z, nt = s.t;
-    bool flip = false;
+    flip = false;
     if constexpr (MU == 0) nx = DIR > 0 ? (s.x + 1 == d.L[0] ? 0 : s.x + 1) : (s.x == 0 ? d.L[0] - 1 : s.x - 1);
     if constexpr (MU == 1) ny = DIR > 0 ? (s.y + 1 == d.L[1] ? 0 : s.y + 1) : (s.y == 0 ? d.L[1] - 1 : s.y - 1);
     if constexpr (MU == 2) nz = DIR > 0 ? (s.z + 1 == d.L[2] ? 0 : s.z + 1) : (s.z == 0 ? d.L[2] - 1 : s.z - 1);
@@ -757,21 +758,22 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
             nt = s.t == 0 ? d.L[3] - 1 : s.t - 1;
         }
     }
-    const int ncb = (nx >> 1) + d.Lxh * (ny + d.L[1] * (nz + d.L[2] * nt));
+    return (nx >> 1) + d.Lxh * (ny + d.L[1] * (nz + d.L[2] * nt));
+}
 
-    // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
-    constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
-    constexpr bool HALF = SP == P_F16 || SP == P_BF16;
-    cpx<T> h0[3], h1[3];
-    T f = 1;
-    if constexpr (HALF) {
-        // projection straight from the packed words; the site norm of the
-        // neighbour and the boundary sign scale the accumulation
+// The spin projection of one neighbour spinor, and the factor its contribution
+// carries: FP16/BF16 are projected straight from the packed words, the site
+// norm and the boundary sign (and the hop coefficient a.scale) ride on the
+// accumulating fma; FP64/FP32 take the boundary sign here and f = 1.
+template <int SP, int MU, int SG, class T>
+WL_HD T project_neighbour(const HopSite &a, int ncb, bool flip, cpx<T> h0[3], cpx<T> h1[3])
+{
+    if constexpr (SP == P_F16 || SP == P_BF16) {
         uint32_t q[12];
         T nrm;
         load_spinor_words<SP>(a.in, a.in_norm, a.stride, ncb, q, &nrm);
         project_half<SP, MU, SG>(q, h0, h1);
-        f = (flip ? -nrm : nrm) * (T)a.scale;
+        return (flip ? -nrm : nrm) * (T)a.scale;
     } else {
         T v[24];
         load_spinor<SP>(a.in, nullptr, a.stride, ncb, v);
@@ -783,22 +785,70 @@ WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s
                 h1[c] = {-h1[c].re, -h1[c].im};
             }
         }
+        return 1;
     }
-    // forward: U_mu(x) on this parity; backward: U_mu(x - mu)^dagger on the other parity
+}
+
+// forward: U_mu(x) on this parity; backward: U_mu(x - mu)^dagger on the other parity
+template <int GP, int R, int MU, int DIR, bool NT, class T>
+WL_HD void hop_link(const HopSite &a, int parity, int cb, int ncb, cpx<T> u[3][3])
+{
     constexpr int NCH = LinkFmt<GP, R>::nchunk;
     const int lpar = DIR > 0 ? parity : 1 - parity;
     const int lcb = DIR > 0 ? cb : ncb;
     const char *lbase = (const char *)a.gauge +
                         (size_t)((lpar * 4 + MU) * NCH) * a.gstride * sizeof(typename LinkFmt<GP, R>::chunk);
-    cpx<T> u[3][3];
     load_link<GP, R, T, NT>(lbase, a.gstride, lcb, u);
+}
+
+// acc += f P (U h0, U h1)
+template <int SP, int MU, int DIR, int SG, class T>
+WL_HD void hop_accumulate(const cpx<T> u[3][3], const cpx<T> h0[3], const cpx<T> h1[3], T f, T acc[24])
+{
     cpx<T> g0[3], g1[3];
     su3_mul<(DIR < 0), T>(u, h0, g0);
     su3_mul<(DIR < 0), T>(u, h1, g1);
-    if constexpr (HALF)
+    if constexpr (SP == P_F16 || SP == P_BF16)
         reconstruct_add_scaled<MU, SG>(acc, g0, g1, f);
     else
         reconstruct_add<MU, SG>(acc, g0, g1);
+}
+
+template <int SP, int GP, int R, int MU, int DIR, bool DAG, bool NT, class T>
+WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s, int cb, T acc[24])
+{
+    bool flip;
+    const int ncb = neighbour<MU, DIR>(d, s, flip);
+    // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
+    constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
+    cpx<T> h0[3], h1[3];
+    const T f = project_neighbour<SP, MU, SG>(a, ncb, flip, h0, h1);
+    cpx<T> u[3][3];
+    hop_link<GP, R, MU, DIR, NT>(a, parity, cb, ncb, u);
+    hop_accumulate<SP, MU, DIR, SG>(u, h0, h1, f, acc);
+}
+
+// The same direction for two right-hand sides of one system at one site: the
+// neighbour index and the link (with its recon-12 row) are formed once.
+template <int SP, int GP, int R, int MU, int DIR, bool DAG, bool NT, class T>
+WL_HD void hop_dir2(const SysDesc &d, const HopSite &a0, const HopSite &a1, int parity, const Site &s, int cb,
+                    T acc0[24], T acc1[24])
+{
+    bool flip;
+    const int ncb = neighbour<MU, DIR>(d, s, flip);
+    constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
+    cpx<T> u[3][3];
+    hop_link<GP, R, MU, DIR, NT>(a0, parity, cb, ncb, u);
+    {
+        cpx<T> h0[3], h1[3];
+        const T f = project_neighbour<SP, MU, SG>(a0, ncb, flip, h0, h1);
+        hop_accumulate<SP, MU, DIR, SG>(u, h0, h1, f, acc0);
+    }
+    {
+        cpx<T> h0[3], h1[3];
+        const T f = project_neighbour<SP, MU, SG>(a1, ncb, flip, h0, h1);
+        hop_accumulate<SP, MU, DIR, SG>(u, h0, h1, f, acc1);
+    }
 }
 
 // Keeps the compiler from hoisting the loads of later directions above this
@@ -842,6 +892,30 @@ WL_HD void hop_site(const SysDesc &d, const HopSite &a, int parity, int cb, T ac
     if constexpr (FENCE == 1) WL_SCHED_FENCE();
     hop_dir<SP, GP, R, 3, -1, DAG, NT>(d, a, parity, s, cb, acc);
     WL_SCHED_FENCE();
+}
+
+// acc0, acc1 = (H psi)(x) of two right-hand sides of one system (a0, a1 name
+// their input vectors), one direction in flight at a time.
+template <int SP, int GP, int R, bool DAG, bool NT = false, class T>
+WL_HD void hop_site2(const SysDesc &d, const HopSite &a0, const HopSite &a1, int parity, int cb, T acc0[24],
+                     T acc1[24])
+{
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc0[k] = acc1[k] = 0;
+    const Site s = cb_coords(d, cb, parity);
+#define WL_DIR2(MU, DIR)                                                                  \
+    hop_dir2<SP, GP, R, MU, DIR, DAG, NT>(d, a0, a1, parity, s, cb, acc0, acc1);          \
+    sched_fence(acc0);                                                                    \
+    sched_fence(acc1);
+    WL_DIR2(0, +1)
+    WL_DIR2(0, -1)
+    WL_DIR2(1, +1)
+    WL_DIR2(1, -1)
+    WL_DIR2(2, +1)
+    WL_DIR2(2, -1)
+    WL_DIR2(3, +1)
+    WL_DIR2(3, -1)
+#undef WL_DIR2
 }
 
 }  // namespace wl

@@ -95,6 +95,9 @@ struct SysEntry {
     double csw = 0.0;  // clover coefficient; 0: Wilson operator
 };
 
+// ExecSet::layout keys at and above this value denote pair layouts
+constexpr int kPairLayout = 1 << 16;
+
 // A set of systems (each a gauge handle with nrhs right-hand sides) whose
 // vectors share every field and every launch.
 class ExecSet {
@@ -111,6 +114,8 @@ public:
 
     // device tables: prec < 0 geometry only; recon 0: no links (geometry and clover term)
     wl_status sys_table(int prec, int recon, hipStream_t s, const SysDesc **out);
+    // B > 0: blocks of B sites of one vector; B < 0: blocks of -B vectors on 64
+    // sites; B >= kPairLayout: blocks of B - kPairLayout sites of two vectors
     wl_status layout(int B, const Layout **out);
     int32_t *d_active = nullptr;
     std::vector<int32_t> h_active;

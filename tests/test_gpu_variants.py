@@ -21,7 +21,8 @@ def force(monkeypatch):
     return set_cfg
 
 
-@pytest.mark.parametrize("var,block", [(v, b) for v in range(6) for b in (64, 512)] + [(6, 256), (6, 512)])
+@pytest.mark.parametrize("var,block", [(v, b) for v in range(6) for b in (64, 512)] + [(6, 256), (6, 512), (7, 64),
+                                                                                         (7, 256)])
 def test_every_hop_variant_matches_oracle(var, block, force):
     w = need_gpu()
     force(var, block)
@@ -52,13 +53,15 @@ def test_every_hop_variant_solves(var, sloppy, force):
     assert st == w.WL_OK and tr <= 1e-10, (var, sloppy, st, info, tr)
 
 
-@pytest.mark.parametrize("block", [256, 512])
+@pytest.mark.parametrize("var,block", [(6, 256), (6, 512), (7, 64), (7, 256)])
 @pytest.mark.parametrize("sloppy", ["f32", "f16"])
-def test_rhs_block_variant_solves(block, sloppy, force):
-    """variant 6 (the waves of a block serve consecutive right-hand sides): 5
-    right-hand sides, so the last block of 4 or 8 is partly empty"""
+def test_rhs_block_variant_solves(var, block, sloppy, force):
+    """variant 6 (the waves of a block serve consecutive right-hand sides) and 7
+    (each thread serves two right-hand sides): 5 right-hand sides, so the last
+    block of 4 or 8, or the last pair, is partly empty; converged right-hand
+    sides drop out one by one"""
     w = need_gpu()
-    force(6, block)
+    force(var, block)
     L = (8, 8, 8, 8)
     U = li.near_identity_links(L, 0.3, 1003)
     eta = li.gaussian_spinor(L, 2003, nrhs=5)
