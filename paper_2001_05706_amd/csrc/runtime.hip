@@ -2,6 +2,7 @@
 // sets, launch helpers, the block-size autotuner, kernel timing, the D-slash
 // entry point and the measurement entry points.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -416,9 +417,22 @@ wl_status ExecSet::layout(int B, const Layout **out)
             hv[vbase + r].pslot0 = ps;
             ps += nb;
         }
-        // logical order (system, site block, rhs): right-hand sides sharing links are adjacent
-        for (int b = 0; b < nb; ++b)
-            for (int r = 0; r < nrhs; r += G) map.push_back(BlkMap{vbase + r, b});
+        // logical order (system, site block, rhs): right-hand sides sharing links
+        // are adjacent.  Site blocks go in time groups of ceil(Lt / 8) slices
+        // (one XCD's contiguous share of the launch), and inside a group in
+        // columns of 4 z-planes swept along t, so a neighbour in t is 4 planes
+        // away in launch order rather than a whole slice: the spinors a wave's
+        // neighbours need are still in the XCD's L2 when they are read.
+        const SysDesc &g = systems[i].g->geom;
+        const int plane = g.Lxh * g.L[1], slice = plane * g.L[2], tg = (g.L[3] + 7) / 8;
+        std::vector<std::array<int, 5>> key(nb);
+        for (int b = 0; b < nb; ++b) {
+            const int cb0 = b * sites, t = cb0 / slice, z = (cb0 % slice) / plane;
+            key[b] = {t / tg, z / 4, t, z, b};
+        }
+        std::sort(key.begin(), key.end());
+        for (int k = 0; k < nb; ++k)
+            for (int r = 0; r < nrhs; r += G) map.push_back(BlkMap{vbase + r, key[k][4]});
         vbase += nrhs;
     }
     L.nblocks = (int)map.size();
