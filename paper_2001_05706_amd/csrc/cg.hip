@@ -11,8 +11,9 @@
 //   b' = eta_e + kappa D_eo eta_o,   M = 1 - kappa^2 D_eo D_oe,
 //   M^+ = 1 - kappa^2 D_oe^+ D_eo^+ (dagger hops in the same order).
 // Iteration (sloppy precision; alpha, beta, gamma stay on the device):
-//   q = M p, alpha = gamma / |q|^2; x += alpha p; r -= alpha q (|r|^2 fused);
-//   s = M^+ r, gamma' = |s|^2, beta = gamma'/gamma; p = s + beta p.
+//   q = M p, alpha = gamma / |q|^2; r -= alpha q (|r|^2 fused);
+//   s = M^+ r, gamma' = |s|^2, beta = gamma'/gamma; x += alpha p and
+//   p = s + beta p in one pass over p.
 // The host reads only the |r|^2 history, once per chunk of iterations.  A
 // chunk is captured once as a HIP graph and replayed.  When the sloppy
 // residual of a right-hand side has fallen by `delta` since its last update

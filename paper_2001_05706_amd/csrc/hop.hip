@@ -18,7 +18,9 @@ namespace wl {
 // Launch variants the autotuner chooses from, with the block size:
 //   fence: directions whose operands may be in flight together per wave
 //   waves: occupancy target (waves per SIMD), which caps registers at 512/waves
-//   nt:    non-temporal link loads (links used once) or cached (shared by RHS)
+//   nt:    non-temporal link loads or cached ones (cached win wherever a cache
+//          line of links is shared: by the right-hand sides of a set, and by
+//          neighbouring waves whose backward-link rows start mid line)
 //   0: fence 2, 4 waves (FP64: 2), non-temporal links
 //   1: fence 1, 5 waves (FP64: 3), non-temporal links
 //   2: fence 1, 6 waves (FP64: 3), non-temporal links
