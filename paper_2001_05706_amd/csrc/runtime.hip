@@ -671,7 +671,10 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         a.red = rs;
         return a;
     };
-    const std::string key = hop_key(S, prec, recon, dag) + (clov ? "/clov" : "");
+    // tuned per epilogue shape: a hop that also reads X fields and reduces may
+    // prefer another variant than a plain one
+    const std::string key = hop_key(S, prec, recon, dag) + (clov ? "/clov" : "") + "/x" + std::to_string(e.nx) +
+                            (red.kind != RED_NONE ? "/r" : "");
     std::vector<int> cands = hop_candidates(prec);
     if (clov)  // the clover epilogue needs the registers of the two-direction variants (0 and 3)
         cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 == 1 || c / 1024 == 2; }),
@@ -684,7 +687,9 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
     const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;
         if (hop_layout(S, c, &L) != WL_OK) return hipErrorOutOfMemory;
-        return launch_hop(prec, recon, dag, clov, c / 1024, mk(L, no_red()), c % 1024, s);
+        // with the launch's own reduction: the partial slots it writes are
+        // rewritten by the launch that follows the tuning
+        return launch_hop(prec, recon, dag, clov, c / 1024, mk(L, red), c % 1024, s);
     });
     const int B = cfg % 1024, var = cfg / 1024;
     const Layout *L = nullptr;
@@ -1122,7 +1127,8 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
         Epi e;
         e.coef = coef;
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
-        cfg = tuned_block(hop_key(*S, prec, recon, false), hop_candidates(prec), s, [](int) { return hipSuccess; });
+        cfg = tuned_block(hop_key(*S, prec, recon, false) + "/x0", hop_candidates(prec), s,
+                          [](int) { return hipSuccess; });
         B = cfg % 1024;
         if (st == WL_OK) st = hop_layout(*S, cfg, &L);
     }
