@@ -626,7 +626,9 @@ std::vector<int> hop_candidates(int prec)
             for (int b : {256, 512}) c.push_back(v * 1024 + b);  // 4 or 8 right-hand sides per block
             continue;
         }
-        if (v == 7 && prec == P_F64) continue;  // two FP64 accumulators do not fit the registers
+        // two FP64 accumulators fit only at 2 waves per SIMD, where variant 7 measured
+        // slower than 3 and 6 (12-RHS recon-12 D-slash: 700 us against 672 us)
+        if (v == 7 && prec == P_F64) continue;
         for (int b : {64, 128, 256, 512}) c.push_back(v * 1024 + b);
     }
     return c;
