@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_clov_inv(BlasArgs a)
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
-    constexpr int CP = P == P_F64 ? P_F64 : P_F32;
+    constexpr int CP = clover_prec<P>();
     T x[24];
     load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
     if (sd.clovinv) clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, x);

@@ -137,7 +137,8 @@ __device__ M3 field_strength(const double *U, const SysDesc &d, long s, const in
 }
 
 // packed block b (36 reals) of the parity-major field at (par, cb)
-__device__ void store_block(void *A64, void *A32, const SysDesc &d, int par, int cb, int b, const double m[36])
+__device__ void store_block(void *A64, void *A32, void *A16, const SysDesc &d, int par, int cb, int b,
+                            const double m[36])
 {
     double2 *f64 = (double2 *)clover_parity<P_F64>(A64, par, d.stride);
     for (int k = 0; k < 18; ++k) f64[(size_t)(18 * b + k) * d.stride + cb] = double2{m[2 * k], m[2 * k + 1]};
@@ -145,9 +146,20 @@ __device__ void store_block(void *A64, void *A32, const SysDesc &d, int par, int
     for (int k = 0; k < 9; ++k)
         f32[(size_t)(9 * b + k) * d.stride + cb] =
             float4{(float)m[4 * k], (float)m[4 * k + 1], (float)m[4 * k + 2], (float)m[4 * k + 3]};
+    // FP16: block b is the 8-byte units 9b .. 9b + 8 of the site's 18 (two per
+    // 16-byte row), so the two blocks of a site, written by different threads,
+    // never share a store
+    char *f16 = (char *)clover_parity<P_F16>(A16, par, d.stride);
+    for (int k = 0; k < 9; ++k) {
+        const int u = 9 * b + k;
+        const uint2 w{pack2<P_F16>((float)m[4 * k], (float)m[4 * k + 1]),
+                      pack2<P_F16>((float)m[4 * k + 2], (float)m[4 * k + 3])};
+        *(uint2 *)(f16 + ((size_t)(u >> 1) * d.stride + cb) * 16 + (u & 1) * 8) = w;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_clover_build(const double *U, SysDesc d, double kc, void *A64, void *A32)
+__global__ __launch_bounds__(256) void k_clover_build(const double *U, SysDesc d, double kc, void *A64, void *A32,
+                                                      void *A16)
 {
     const long V = 2L * d.Vh;
     const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,12 +204,13 @@ __global__ __launch_bounds__(256) void k_clover_build(const double *U, SysDesc d
                             }
                     }
         }
-    store_block(A64, A32, d, par, cb, 0, m[0]);
-    store_block(A64, A32, d, par, cb, 1, m[1]);
+    store_block(A64, A32, A16, d, par, cb, 0, m[0]);
+    store_block(A64, A32, A16, d, par, cb, 1, m[1]);
 }
 
 // one thread per (site, block): the inverse of a Hermitian 6x6 block
-__global__ __launch_bounds__(256) void k_clover_invert(SysDesc d, const void *A64, void *Ainv64, void *Ainv32)
+__global__ __launch_bounds__(256) void k_clover_invert(SysDesc d, const void *A64, void *Ainv64, void *Ainv32,
+                                                       void *Ainv16)
 {
     const long n = 2L * 2L * d.Vh;  // (parity, cb, block)
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -264,23 +277,26 @@ __global__ __launch_bounds__(256) void k_clover_invert(SysDesc d, const void *A6
             q[u + 1] = a[i][6 + j].im;
         }
     }
-    store_block(Ainv64, Ainv32, d, par, cb, b, q);
+    store_block(Ainv64, Ainv32, Ainv16, d, par, cb, b, q);
 }
 
 }  // namespace
 
-hipError_t launch_clover_build(const double *U_canon, const SysDesc &d, double kc, void *A64, void *A32,
+hipError_t launch_clover_build(const double *U_canon, const SysDesc &d, double kc, void *A64, void *A32, void *A16,
                                hipStream_t s)
 {
     const long V = 2L * d.Vh;
-    hipLaunchKernelGGL(k_clover_build, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, U_canon, d, kc, A64, A32);
+    hipLaunchKernelGGL(k_clover_build, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, s, U_canon, d, kc, A64, A32,
+                       A16);
     return hipGetLastError();
 }
 
-hipError_t launch_clover_invert(const SysDesc &d, const void *A64, void *Ainv64, void *Ainv32, hipStream_t s)
+hipError_t launch_clover_invert(const SysDesc &d, const void *A64, void *Ainv64, void *Ainv32, void *Ainv16,
+                                hipStream_t s)
 {
     const long n = 4L * d.Vh;
-    hipLaunchKernelGGL(k_clover_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, A64, Ainv64, Ainv32);
+    hipLaunchKernelGGL(k_clover_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, A64, Ainv64, Ainv32,
+                       Ainv16);
     return hipGetLastError();
 }
 

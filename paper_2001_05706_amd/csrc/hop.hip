@@ -67,8 +67,8 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd
         for (int k = 0; k < 24; ++k) acc[k] *= c;
     }
 
-    // clover term of this system at the output site (FP16/BF16 launches use the FP32 copy)
-    constexpr int CP = SP == P_F64 ? P_F64 : P_F32;
+    // clover term of this system at the output site (FP16/BF16 launches read the FP16 copy)
+    constexpr int CP = clover_prec<SP>();
     const bool clov = CLOV && a.epi.clov != 0 && sd.clov != nullptr;
     T o[24];
     if (a.epi.nx >= 1) {

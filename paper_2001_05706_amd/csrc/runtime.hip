@@ -202,7 +202,7 @@ wl_gauge_s::~wl_gauge_s()
     for (auto &a : packed)
         for (auto &p : a) (void)hipFree(p);
     for (auto &c : clovers)
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 3; ++k) {
             (void)hipFree(c.A[k]);
             (void)hipFree(c.Ainv[k]);
         }
@@ -232,7 +232,7 @@ wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const voi
 
 wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const void **A, const void **Ainv)
 {
-    const int k = prec == P_F64 ? 0 : 1;
+    const int k = prec == P_F64 ? 0 : prec == P_F32 ? 1 : 2;
     for (auto &c : g->clovers)
         if (c.kc == kc) {
             *A = c.A[k];
@@ -240,25 +240,25 @@ wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const voi
             return WL_OK;
         }
     if (capturing(s)) return set_error(WL_ERR_HIP, "clover term first needed inside a graph capture");
-    wl_gauge_s::Clover c{kc, {nullptr, nullptr}, {nullptr, nullptr}};
+    wl_gauge_s::Clover c{kc, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     const size_t per = (size_t)2 * g->geom.stride * 72;  // reals of one field, both parities
     bool ok = true;
-    for (int j = 0; j < 2 && ok; ++j) {
-        const size_t bytes = per * (j == 0 ? sizeof(double) : sizeof(float));
+    for (int j = 0; j < 3 && ok; ++j) {
+        const size_t bytes = per * (j == 0 ? 8 : j == 1 ? 4 : 2);
         ok = hipMalloc(&c.A[j], bytes) == hipSuccess && hipMalloc(&c.Ainv[j], bytes) == hipSuccess;
         if (ok) ok = hipMemsetAsync(c.A[j], 0, bytes, s) == hipSuccess && hipMemsetAsync(c.Ainv[j], 0, bytes, s) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 3; ++j) {
             (void)hipFree(c.A[j]);
             (void)hipFree(c.Ainv[j]);
         }
         return set_error(WL_ERR_NOMEM, "cannot allocate the clover term");
     }
     g->clovers.push_back(c);
-    WL_HIP(launch_clover_build(g->U, g->geom, kc, c.A[0], c.A[1], s));
-    WL_HIP(launch_clover_invert(g->geom, c.A[0], c.Ainv[0], c.Ainv[1], s));
+    WL_HIP(launch_clover_build(g->U, g->geom, kc, c.A[0], c.A[1], c.A[2], s));
+    WL_HIP(launch_clover_invert(g->geom, c.A[0], c.Ainv[0], c.Ainv[1], c.Ainv[2], s));
     *A = c.A[k];
     *Ainv = c.Ainv[k];
     return WL_OK;
@@ -588,8 +588,9 @@ double hop_bytes(const ExecSet &S, int prec, int recon, bool use_active)
 
 double clover_bytes(const ExecSet &S, int prec, bool use_active)
 {
-    // 72 reals per site, FP64 for FP64 launches and FP32 otherwise, shared by the RHS of a system
-    const double site = 72.0 * (prec == P_F64 ? 8 : 4);
+    // 72 reals per site in the copy the launch reads (FP64, FP32, FP16 for FP16/BF16),
+    // shared by the RHS of a system
+    const double site = 72.0 * (prec == P_F64 ? 8 : prec == P_F32 ? 4 : 2);
     double b = 0;
     for (size_t i = 0; i < S.systems.size(); ++i)
         if (S.systems[i].csw != 0.0 && any_active_in(S, (int)i, use_active)) b += site * S.systems[i].g->geom.Vh;

@@ -441,7 +441,8 @@ struct SysDesc {
 // 2b, 2b+1 (all colours), i.e. on the 12 reals o[12b .. 12b+11].  A block is
 // packed as 36 reals: the 6 real diagonal entries, then the 15 entries above
 // the diagonal in row-major order as (re, im).  FP64 stores 36 double2 rows per
-// site, FP32 18 float4 rows (FP16/BF16 launches use the FP32 copy).
+// site, FP32 18 float4 rows, FP16 9 uint4 rows of 8 halves (the 72 reals of the
+// two blocks in order; FP16 and BF16 launches read this copy).
 template <int P> struct CloverFmt {
     using chunk = float4;
     static constexpr int nchunk = 18;
@@ -450,6 +451,13 @@ template <> struct CloverFmt<P_F64> {
     using chunk = double2;
     static constexpr int nchunk = 36;
 };
+template <> struct CloverFmt<P_F16> {
+    using chunk = uint4;
+    static constexpr int nchunk = 9;
+};
+
+// the copy of the clover term a launch of storage precision P reads
+template <int P> constexpr int clover_prec() { return P == P_F64 ? P_F64 : P == P_F32 ? P_F32 : P_F16; }
 
 // packed index of entry (i, j), i < j, of a 6x6 block
 WL_HD int clov_upper(int i, int j) { return 6 + 2 * (i * 6 - i * (i + 1) / 2 + (j - i - 1)); }
@@ -459,10 +467,27 @@ template <int P, class T>
 WL_HD void clover_apply(const void *base, int stride, int cb, T o[24])
 {
     using CF = CloverFmt<P>;
+    uint32_t h[36];  // FP16: the site's 72 halves, two per word
+    if constexpr (P == P_F16) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const uint4 w = *row_elem<uint4>(base, c, stride, cb);
+            h[4 * c] = w.x;
+            h[4 * c + 1] = w.y;
+            h[4 * c + 2] = w.z;
+            h[4 * c + 3] = w.w;
+        }
+    }
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         T m[36];
-        if constexpr (P == P_F64) {
+        if constexpr (P == P_F16) {
+#pragma unroll
+            for (int k = 0; k < 36; ++k) {
+                const int e = 36 * b + k;
+                m[k] = (T)(e & 1 ? hi16_to_float<P_F16>(h[e >> 1]) : lo16_to_float<P_F16>(h[e >> 1]));
+            }
+        } else if constexpr (P == P_F64) {
 #pragma unroll
             for (int c = 0; c < 18; ++c) {
                 const double2 w = *row_elem<double2>(base, 18 * b + c, stride, cb);

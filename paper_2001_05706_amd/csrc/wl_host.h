@@ -55,11 +55,11 @@ struct wl_gauge_s {
     int device = 0;
     double *U = nullptr;       // canonical FP64 copy (device)
     void *packed[4][2] = {};   // [prec][recon == 12]
-    // clover term A and A^{-1} per value of kappa * c_sw, FP64 [0] and FP32 [1]
+    // clover term A and A^{-1} per value of kappa * c_sw, FP64 [0], FP32 [1], FP16 [2]
     struct Clover {
         double kc;
-        void *A[2];
-        void *Ainv[2];
+        void *A[3];
+        void *Ainv[3];
     };
     std::vector<Clover> clovers;
     ~wl_gauge_s();
@@ -69,7 +69,7 @@ namespace wl {
 
 wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const void **out);
 // packed clover term A and A^{-1} for kappa * c_sw = kc in the storage a hop of
-// precision prec reads (FP64 for FP64, FP32 otherwise), built on first use
+// precision prec reads (FP64, FP32, and FP16 for FP16/BF16), built on first use
 wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const void **A, const void **Ainv);
 
 // ------------------------------------------------------------------ execution sets

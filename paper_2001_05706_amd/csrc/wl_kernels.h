@@ -84,10 +84,11 @@ hipError_t launch_pack_gauge(int prec, int recon, const double *U_canon, void *o
                              hipStream_t s);
 
 // clover.hip: A = 1 + i kc sum_{m<n} s_mn F_mn from the canonical links, packed
-// FP64 and FP32; then A^{-1} from the FP64 A
-hipError_t launch_clover_build(const double *U_canon, const SysDesc &d, double kc, void *A64, void *A32,
+// FP64, FP32 and FP16; then A^{-1} from the FP64 A
+hipError_t launch_clover_build(const double *U_canon, const SysDesc &d, double kc, void *A64, void *A32, void *A16,
                                hipStream_t s);
-hipError_t launch_clover_invert(const SysDesc &d, const void *A64, void *Ainv64, void *Ainv32, hipStream_t s);
+hipError_t launch_clover_invert(const SysDesc &d, const void *A64, void *Ainv64, void *Ainv32, void *Ainv16,
+                                hipStream_t s);
 hipError_t launch_copy_bw(const void *in, void *out, size_t bytes, hipStream_t s);
 
 }  // namespace wl

@@ -38,6 +38,24 @@ def test_clover_dslash_matches_oracle(links, prec, recon, gate, dagger):
     g.close()
 
 
+@pytest.mark.parametrize("prec,gate", [("f16", 5e-3), ("bf16", 3e-2)])
+@pytest.mark.parametrize("dagger", [0, 1])
+def test_clover_dslash_half_precision(links, prec, gate, dagger):
+    """FP16/BF16 storage reads the FP16 copy of the clover term: the error
+    against the FP64 oracle stays at the storage rounding of spinors, links and
+    clover entries (2^-11 relative for FP16, 2^-8 for BF16)."""
+    w = need_gpu()
+    psi = li.gaussian_spinor(L, 2305, nrhs=2)
+    ref = oracle.wilson_clover(L, links, psi, KAPPA, CSW, dagger=bool(dagger))
+    g = w.Gauge(L, to_dev(links))
+    out = to_dev(np.zeros_like(psi))
+    w.wilson_clover_dslash(g, to_dev(psi), out, 2, KAPPA, CSW, dagger, prec, 12)
+    got = from_dev(out, psi.shape)
+    for r in range(2):
+        assert rel(got[r], ref[r]) <= gate, (r, rel(got[r], ref[r]))
+    g.close()
+
+
 @pytest.mark.parametrize("method", ["cg", "bicgstab"])
 @pytest.mark.parametrize("sloppy,recon", [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)])
 def test_clover_solve_matches_oracle(links, method, sloppy, recon):
