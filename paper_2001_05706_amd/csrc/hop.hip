@@ -172,9 +172,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
         if (a.active && !a.active[bm.v]) return;
         cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
     }
-    const unsigned long long t_start = a.stamps ? (unsigned long long)wall_clock64() : 0ull;
     const VecDesc vd = a.vec[valid ? v : bm.v];
     const SysDesc sd = a.sys[vd.sys];
+    // the block's start stamp goes to memory at once, after the descriptor
+    // loads are issued (held in registers across the body, or read before
+    // them, it costs the FP16 kernel four registers and a spill)
+    if (a.stamps && threadIdx.x == 0) a.stamps[2 * lb] = (unsigned long long)wall_clock64();
 
     if constexpr (PAIR) {
         // vectors bm.v and bm.v + 1 (when that is a further rhs of the same
@@ -213,10 +216,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     if (a.stamps) {
         // the block's work ends when its last wave ends
         __syncthreads();
-        if (threadIdx.x == 0) {
-            a.stamps[2 * lb] = t_start;
-            a.stamps[2 * lb + 1] = (unsigned long long)wall_clock64();
-        }
+        if (threadIdx.x == 0) a.stamps[2 * lb + 1] = (unsigned long long)wall_clock64();
     }
 }
 
