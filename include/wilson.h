@@ -158,7 +158,8 @@ wl_status wilson_cg_multi(int32_t nsys, const wl_gauge *U, const double *const *
  * with Q_mn(x) the four plaquettes of the m-n plane with a corner at x (each a
  * loop from x, m-direction first).  A is built on the GPU from the handle's
  * links on first use for each value of kappa c_sw and kept with the handle
- * (FP64 and FP32 copies of A and A^{-1}: 2 x 864 bytes per site).  c_sw = 0
+ * (FP64, FP32 and FP16 copies of A and A^{-1}: 2 x 1008 bytes per site; FP16
+ * and BF16 launches read the FP16 copy).  c_sw = 0
  * gives the Wilson operator.  Layouts, streams and errors as for the Wilson
  * entry points. */
 
