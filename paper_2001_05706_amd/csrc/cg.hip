@@ -427,9 +427,10 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
             WL_TRY(cg.chunk(k));
             cg.use_graphs = graphs;
             first = false;
-            WL_HIP(hipMemcpyAsync(hp, S.hist, sizeof(double) * k * nv, hipMemcpyDeviceToHost, s));
+            // the k history rows and the flags behind the whole history, in one copy
+            WL_HIP(hipMemcpyAsync(hp, S.hist, sizeof(double) * ExecSet::kHist * nv + sizeof(int32_t) * nv,
+                                  hipMemcpyDeviceToHost, s));
             int32_t *hbad = (int32_t *)(hp + (size_t)ExecSet::kHist * nv);
-            WL_HIP(hipMemcpyAsync(hbad, S.bad, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, s));
             WL_HIP(hipStreamSynchronize(s));
             if (trace) {
                 double sc[ExecSet::SC_N];

@@ -289,8 +289,7 @@ ExecSet::~ExecSet()
     (void)hipFree(partials);
     (void)hipFree(counters);
     (void)hipFree(sc);
-    (void)hipFree(bad);
-    (void)hipFree(hist);
+    (void)hipFree(hist);  // bad lives at its end
     (void)hipFree(hist_partials);
     (void)hipHostFree(h_pinned);
     (void)hipHostFree(h_masks);
@@ -332,8 +331,10 @@ wl_status ExecSet::init()
     WL_ALLOC(partials, sizeof(double) * 3 * max_pslots);
     WL_ALLOC(counters, sizeof(uint32_t) * nvec);
     WL_ALLOC(sc, sizeof(double) * SC_N * nvec);
-    WL_ALLOC(bad, sizeof(int32_t) * nvec);
-    WL_ALLOC(hist, sizeof(double) * kHist * nvec);
+    // the flags follow the history in one allocation, so that the host reads
+    // both with one copy (the same layout as the pinned mirror)
+    WL_ALLOC(hist, sizeof(double) * kHist * nvec + sizeof(int32_t) * nvec);
+    bad = (int32_t *)(hist + (size_t)kHist * nvec);
     WL_ALLOC(hist_partials, sizeof(double) * kHist * max_pslots);
     if (hipHostMalloc((void **)&h_pinned, sizeof(double) * (kHist + SC_N + 1) * nvec + 64, 0) != hipSuccess) {
         (void)hipGetLastError();

@@ -130,8 +130,8 @@ public:
     double *partials = nullptr;  // max slots over layouts (B = 64), 3 values each
     uint32_t *counters = nullptr;
     double *sc = nullptr;        // scalar arena, see SC_* below
-    int32_t *bad = nullptr;
-    double *hist = nullptr;      // residual history: [kHist][nvec]
+    int32_t *bad = nullptr;      // at the end of the hist allocation
+    double *hist = nullptr;      // residual history: [kHist][nvec], then bad
     double *hist_partials = nullptr;  // deferred block partials of the history: [kHist][max_pslots]
     double *h_pinned = nullptr;  // pinned host mirror of hist, scalars and flags
     static constexpr int kHist = 64;
