@@ -10,11 +10,11 @@ residual.  Inputs are resident in HBM before the timed region.
 
 value  = algorithmic HBM bytes of every kernel of the solve / solve time (GB/s)
 roofline = the dominant kernel (the single-parity hop): algorithmic bytes per
-           launch / mean kernel duration (device steady-clock span of every hop
-           of the solver; HIP-event dispatch intervals reported beside it),
-           against the 8 TB/s HBM peak; traffic = the
-           committed rocprofv3 counter reading per launch while the hop's
-           sources are unchanged
+           launch / mean launch duration (HIP events recorded by each hop's
+           dispatch on the solver's stream; the device steady-clock span of
+           the same launches reported beside it), against the 8 TB/s HBM peak;
+           traffic = the committed rocprofv3 counter reading per launch while
+           the hop's sources are unchanged
 cpu_baseline = the FP64 CPU oracle's CGNR solve of the same system, in the same
            byte model.
 
@@ -326,10 +326,10 @@ def main():
     assert all(i["converged"] for i in infos) and worst <= tol
 
     # ---- per-kernel timing of the dominant kernel over the same K solves (the
-    # solver runs without graphs while timing is on): each hop's blocks record
-    # the device steady clock at their start and end (the kernel's own span),
-    # and HIP events recorded by its dispatch on the solver's stream give the
-    # dispatch-to-completion interval beside it
+    # solver runs without graphs while timing is on): HIP events recorded by
+    # each hop's dispatch on the solver's stream give its launch duration (the
+    # roofline's), and the blocks' device steady-clock stamps (first block
+    # start to last block end) its own span beside it
     w.wl_prof_enable(True)
     w.wl_prof_select(a.sloppy)  # the dominant kernel: the sloppy-precision hop
     w.wl_prof_read()
@@ -339,11 +339,11 @@ def main():
     n_hop, hop_ms, hop_gb, hop_kms = w.wl_prof_read()
     w.wl_prof_enable(False)
     w.wl_prof_select(-1)
-    hop_avg_us = hop_kms * 1e3 / max(n_hop, 1)         # kernel span, device steady clock
-    hop_event_us = hop_ms * 1e3 / max(n_hop, 1)        # dispatch to completion, HIP events
-    achieved = hop_gb / (hop_kms * 1e-3) if hop_kms > 0 else 0.0
-    log("hop launches %d, mean kernel %.2f us (events %.2f us), %.1f GB/s" %
-        (n_hop, hop_avg_us, hop_event_us, achieved))
+    hop_event_us = hop_ms * 1e3 / max(n_hop, 1)        # launch duration, HIP events
+    hop_span_us = hop_kms * 1e3 / max(n_hop, 1)        # kernel span, device steady clock
+    achieved = hop_gb / (hop_ms * 1e-3) if hop_ms > 0 else 0.0
+    log("hop launches %d, mean launch %.2f us (HIP events; span %.2f us on the steady clock), %.1f GB/s" %
+        (n_hop, hop_event_us, hop_span_us, achieved))
 
     out = {
         "metric": METRIC,
@@ -378,8 +378,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(a.sloppy, a.recon),
-            "mean_launch_us": round(hop_avg_us, 3),
-            "mean_dispatch_us_events": round(hop_event_us, 3),
+            "mean_launch_us": round(hop_event_us, 3),
+            "mean_span_us_clock": round(hop_span_us, 3),
             "launches": n_hop,
         },
     }
