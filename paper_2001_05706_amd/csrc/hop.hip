@@ -169,11 +169,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     } else if constexpr (PAIR) {
         cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
     } else {
-        if (a.active && !a.active[bm.v]) return;
+        if (a.active && !a.active[a.one ? 0 : bm.v]) return;
         cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;
     }
-    const VecDesc vd = a.vec[valid ? v : bm.v];
-    const SysDesc sd = a.sys[vd.sys];
+    // (single-vector sets: the indices are known, so the descriptor loads do
+    // not wait for the block map)
+    const VecDesc vd = a.vec[a.one ? 0 : (valid ? v : bm.v)];
+    const SysDesc sd = a.sys[a.one ? 0 : vd.sys];
     // the block's start stamp goes to memory at once, after the descriptor
     // loads are issued (held in registers across the body, or read before
     // them, it costs the FP16 kernel four registers and a spill)

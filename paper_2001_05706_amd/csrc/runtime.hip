@@ -673,6 +673,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
             a.epi.Xn[j] = e.X[j].n;
         }
         a.red = rs;
+        a.one = S.nvec == 1;
         return a;
     };
     // tuned per epilogue shape: a hop that also reads X fields and reduces may
@@ -1155,6 +1156,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
             a.out_norm = fout[k].n;
             a.epi.coef = coef;
             a.red = no_red();
+            a.one = S->nvec == 1;  // as the solvers launch it
             return launch_hop(prec, recon, false, false, cfg / 1024, a, B, s);
         };
         for (int k = 0; k < nsets && st == WL_OK; ++k)

@@ -123,6 +123,10 @@ struct HopArgs {
     // kernel timing (null: off): each block stores its first and last steady-clock
     // reading at stamps[2 * logical block + {0, 1}]
     unsigned long long *stamps;
+    // one == 1: the set is a single vector (vector 0 of system 0), so a block
+    // loads its descriptors without waiting for the block map
+    int32_t one;
+    int32_t pad1_;
 };
 
 }  // namespace wl
