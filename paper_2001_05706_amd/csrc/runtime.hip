@@ -287,7 +287,6 @@ ExecSet::~ExecSet()
     }
     (void)hipFree(d_active);
     (void)hipFree(partials);
-    (void)hipFree(counters);
     (void)hipFree(sc);
     (void)hipFree(hist);  // bad lives at its end
     (void)hipFree(hist_partials);
@@ -329,7 +328,6 @@ wl_status ExecSet::init()
     h_active.assign(nvec, 1);
     WL_ALLOC(d_active, sizeof(int32_t) * nvec);
     WL_ALLOC(partials, sizeof(double) * 3 * max_pslots);
-    WL_ALLOC(counters, sizeof(uint32_t) * nvec);
     WL_ALLOC(sc, sizeof(double) * SC_N * nvec);
     // the flags follow the history in one allocation, so that the host reads
     // both with one copy (the same layout as the pinned mirror)
@@ -348,7 +346,6 @@ wl_status ExecSet::init()
     }
     for (auto &e : mask_ev) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     WL_HIP(hipMemcpy(d_active, h_active.data(), sizeof(int32_t) * nvec, hipMemcpyHostToDevice));
-    WL_HIP(hipMemset(counters, 0, sizeof(uint32_t) * nvec));
     WL_HIP(hipMemset(sc, 0, sizeof(double) * SC_N * nvec));
     WL_HIP(hipMemset(bad, 0, sizeof(int32_t) * nvec));
     WL_HIP(hipMemset(hist, 0, sizeof(double) * kHist * nvec));

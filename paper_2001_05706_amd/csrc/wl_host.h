@@ -128,7 +128,6 @@ public:
 
     // reduction state (per vector unless noted)
     double *partials = nullptr;  // max slots over layouts (B = 64), 3 values each
-    uint32_t *counters = nullptr;
     double *sc = nullptr;        // scalar arena, see SC_* below
     int32_t *bad = nullptr;      // at the end of the hist allocation
     double *hist = nullptr;      // residual history: [kHist][nvec], then bad
