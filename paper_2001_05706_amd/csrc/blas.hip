@@ -11,12 +11,27 @@
 
 namespace wl {
 
+// Takes the descriptor values as operands, so that their loads are all issued
+// before this point (the compiler would otherwise sink each load to its first
+// use behind the early exits, one memory round trip after another).
+__device__ __forceinline__ void blas_issued(int a, int b, int c, int d, int e)
+{
+    asm volatile("" ::"s"(a), "s"(b), "s"(c), "s"(d), "s"(e));
+}
+
+// The block's vector vi, its descriptors and its logical block.  Every kernel
+// has the template flag ONE: instantiated true for a set of one vector, whose
+// descriptors sit at index 0, so that their loads and the block map's go out
+// together (two dependent rounds fewer at the start of every wave).
 #define WL_BLAS_PROLOGUE                                              \
     const int lb = xcd_remap(blockIdx.x, a.nblocks);                  \
     const BlkMap bm = a.map[lb];                                      \
-    if (a.active && !a.active[bm.v]) return;                          \
-    const VecDesc vd = a.vec[bm.v];                                   \
-    const SysDesc sd = a.sys[vd.sys];                                 \
+    const int vi = ONE ? 0 : bm.v;                                    \
+    const VecDesc vd = a.vec[vi];                                     \
+    const SysDesc sd = a.sys[ONE ? 0 : vd.sys];                       \
+    const int act = a.active ? a.active[vi] : 1;                      \
+    if constexpr (ONE) blas_issued(bm.lblk, vd.site_off, sd.Vh, sd.stride, act); \
+    if (!act) return;                                                 \
     const int cb = bm.lblk * (int)blockDim.x + (int)threadIdx.x;      \
     const bool live = cb < sd.Vh;
 
@@ -36,14 +51,14 @@ template <int P> __device__ __forceinline__ const void *fbase(const BlasArgs &a,
     return (a.bcast >> j) & 1 ? a.f[j] : vbase<P>(a.f[j], vd);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     double nrm = 0.0;
     if (live) {
-        const T al = (T)a.s0[bm.v];
+        const T al = (T)a.s0[vi];
         T x[24], p[24], r[24], q[24];
         load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
         load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, p);
@@ -61,13 +76,13 @@ __global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
     if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_xpay(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
-    const T be = (T)a.s0[bm.v];
+    const T be = (T)a.s0[vi];
     T p[24], s[24];
     load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
     load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
@@ -78,14 +93,14 @@ __global__ __launch_bounds__(256) void k_xpay(BlasArgs a)
 
 // CGNR with the solution update folded into the direction update: the
 // residual step alone here, x += alpha p with p = s + beta p below
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     double nrm = 0.0;
     if (live) {
-        const T al = (T)a.s0[bm.v];
+        const T al = (T)a.s0[vi];
         T r[24], q[24];
         load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
         load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, q);
@@ -97,14 +112,14 @@ __global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
     if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
-    const T be = (T)a.s0[bm.v];
-    const T al = (T)a.sc[SC_ALPHA * a.nvec + bm.v];
+    const T be = (T)a.s0[vi];
+    const T al = (T)a.sc[SC_ALPHA * a.nvec + vi];
     T p[24], s[24], x[24];
     load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
     load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
@@ -118,7 +133,7 @@ __global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_accum(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -137,7 +152,7 @@ __global__ __launch_bounds__(256) void k_accum(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, x);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_norm2(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -151,7 +166,7 @@ __global__ __launch_bounds__(256) void k_norm2(BlasArgs a)
     block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_zero(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -163,7 +178,7 @@ __global__ __launch_bounds__(256) void k_zero(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_fill(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -181,13 +196,13 @@ __global__ __launch_bounds__(256) void k_fill(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_scale_rsqrt(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
-    const double n2 = a.s0[bm.v];
+    const double n2 = a.s0[vi];
     const T f = (T)(n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0);
     T x[24];
     load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
@@ -213,17 +228,17 @@ template <class T> __device__ __forceinline__ void cmul_site(T zr, T zi, const T
     }
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
     double rr, ri, pr, pi, ar, ai, orr, oi;
-    cscal(a, SC_RHO_RE, bm.v, rr, ri);
-    cscal(a, SC_RHOP_RE, bm.v, pr, pi);
-    cscal(a, SC_AL_RE, bm.v, ar, ai);
-    cscal(a, SC_OM_RE, bm.v, orr, oi);
+    cscal(a, SC_RHO_RE, vi, rr, ri);
+    cscal(a, SC_RHOP_RE, vi, pr, pi);
+    cscal(a, SC_AL_RE, vi, ar, ai);
+    cscal(a, SC_OM_RE, vi, orr, oi);
     // beta = (rho / rho_prev) (alpha / omega)
     const double d1 = pr * pr + pi * pi, d2 = orr * orr + oi * oi;
     const double q1r = (rr * pr + ri * pi) / d1, q1i = (ri * pr - rr * pi) / d1;
@@ -242,14 +257,14 @@ __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
     double ar, ai;
-    cscal(a, SC_AL_RE, bm.v, ar, ai);
+    cscal(a, SC_AL_RE, vi, ar, ai);
     T r[24], v[24], av[24];
     load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
     load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
@@ -259,7 +274,7 @@ __global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_bicg_xr(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -267,8 +282,8 @@ __global__ __launch_bounds__(256) void k_bicg_xr(BlasArgs a)
     double rv[3] = {0.0, 0.0, 0.0};
     if (live) {
         double ar, ai, orr, oi;
-        cscal(a, SC_AL_RE, bm.v, ar, ai);
-        cscal(a, SC_OM_RE, bm.v, orr, oi);
+        cscal(a, SC_AL_RE, vi, ar, ai);
+        cscal(a, SC_OM_RE, vi, orr, oi);
         T x[24], y[24], z[24], w[24];
         load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
         load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, y);  // p
@@ -292,7 +307,7 @@ __global__ __launch_bounds__(256) void k_bicg_xr(BlasArgs a)
     block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
 }
 
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_cdot(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -308,13 +323,13 @@ __global__ __launch_bounds__(256) void k_cdot(BlasArgs a)
 }
 
 // y += z x (G5: y += z g5 x) with the complex z of this vector from s0
-template <int P, bool G5>
+template <int P, bool G5, bool ONE = false>
 __global__ __launch_bounds__(256) void k_caxpy(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
     WL_BLAS_PROLOGUE
     if (!live) return;
-    const T zr = (T)a.s0[2 * bm.v], zi = (T)a.s0[2 * bm.v + 1];
+    const T zr = (T)a.s0[2 * vi], zi = (T)a.s0[2 * vi + 1];
     T x[24], y[24];
     load_spinor<P>(fbase<P>(a, 1, vd), nbase(a.fn[1], vd), sd.stride, cb, x);
     load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, y);
@@ -329,7 +344,7 @@ __global__ __launch_bounds__(256) void k_caxpy(BlasArgs a)
 
 // y_v = sum_j T[j + nvec v] x_j over the vectors j of a single-system set
 // (vector j starts j strides into the field); T complex in s0
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_rot(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -340,7 +355,7 @@ __global__ __launch_bounds__(256) void k_rot(BlasArgs a)
 #pragma unroll
     for (int k = 0; k < 24; ++k) y[k] = 0;
     for (int j = 0; j < a.nvec; ++j) {
-        const double *t = a.s0 + 2 * ((size_t)j + (size_t)a.nvec * bm.v);
+        const double *t = a.s0 + 2 * ((size_t)j + (size_t)a.nvec * vi);
         const T tr = (T)t[0], ti = (T)t[1];
         T x[24];
         load_spinor<P>((const CH *)a.f[1] + (size_t)j * sd.stride * SpinorFmt<P>::nchunk,
@@ -355,7 +370,7 @@ __global__ __launch_bounds__(256) void k_rot(BlasArgs a)
 }
 
 // y = g5 x: spins 2 and 3 (the last 12 reals of a site) change sign
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_g5copy(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -370,7 +385,7 @@ __global__ __launch_bounds__(256) void k_g5copy(BlasArgs a)
 
 // y = A^{-1} x at the sites of parity a.parity (FP64 term for FP64 fields,
 // FP32 otherwise); systems without a clover term copy
-template <int P>
+template <int P, bool ONE = false>
 __global__ __launch_bounds__(256) void k_clov_inv(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -383,7 +398,7 @@ __global__ __launch_bounds__(256) void k_clov_inv(BlasArgs a)
     store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
 }
 
-template <int PD, int PS>
+template <int PD, int PS, bool ONE = false>
 __global__ __launch_bounds__(256) void k_convert(BlasArgs a)
 {
     using TS = typename SpinorFmt<PS>::real;
@@ -403,25 +418,46 @@ static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_
 {
     dim3 g(a.nblocks), b(block);
     switch (op) {
-    case BL_CG_UPDATE: hipLaunchKernelGGL(k_cg_update<P>, g, b, 0, s, a); break;
-    case BL_XPAY: hipLaunchKernelGGL(k_xpay<P>, g, b, 0, s, a); break;
+    case BL_CG_UPDATE:
+        if (a.one) hipLaunchKernelGGL((k_cg_update<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_cg_update<P>, g, b, 0, s, a);
+        break;
+    case BL_XPAY:
+        if (a.one) hipLaunchKernelGGL((k_xpay<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_xpay<P>, g, b, 0, s, a);
+        break;
     case BL_ACCUM: hipLaunchKernelGGL(k_accum<P>, g, b, 0, s, a); break;
     case BL_NORM2: hipLaunchKernelGGL(k_norm2<P>, g, b, 0, s, a); break;
     case BL_ZERO: hipLaunchKernelGGL(k_zero<P>, g, b, 0, s, a); break;
     case BL_COPY: hipLaunchKernelGGL((k_convert<P, P>), g, b, 0, s, a); break;
     case BL_FILL: hipLaunchKernelGGL(k_fill<P>, g, b, 0, s, a); break;
     case BL_SCALE_RSQRT: hipLaunchKernelGGL(k_scale_rsqrt<P>, g, b, 0, s, a); break;
-    case BL_BICG_P: hipLaunchKernelGGL(k_bicg_p<P>, g, b, 0, s, a); break;
-    case BL_BICG_S: hipLaunchKernelGGL(k_bicg_s<P>, g, b, 0, s, a); break;
-    case BL_BICG_XR: hipLaunchKernelGGL(k_bicg_xr<P>, g, b, 0, s, a); break;
+    case BL_BICG_P:
+        if (a.one) hipLaunchKernelGGL((k_bicg_p<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_bicg_p<P>, g, b, 0, s, a);
+        break;
+    case BL_BICG_S:
+        if (a.one) hipLaunchKernelGGL((k_bicg_s<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_bicg_s<P>, g, b, 0, s, a);
+        break;
+    case BL_BICG_XR:
+        if (a.one) hipLaunchKernelGGL((k_bicg_xr<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_bicg_xr<P>, g, b, 0, s, a);
+        break;
     case BL_CDOT: hipLaunchKernelGGL(k_cdot<P>, g, b, 0, s, a); break;
     case BL_G5COPY: hipLaunchKernelGGL(k_g5copy<P>, g, b, 0, s, a); break;
     case BL_CLOV_INV: hipLaunchKernelGGL(k_clov_inv<P>, g, b, 0, s, a); break;
     case BL_CAXPY: hipLaunchKernelGGL((k_caxpy<P, false>), g, b, 0, s, a); break;
     case BL_CAXPY_G5: hipLaunchKernelGGL((k_caxpy<P, true>), g, b, 0, s, a); break;
     case BL_ROT: hipLaunchKernelGGL(k_rot<P>, g, b, 0, s, a); break;
-    case BL_R_UPDATE: hipLaunchKernelGGL(k_r_update<P>, g, b, 0, s, a); break;
-    case BL_XPAY_X: hipLaunchKernelGGL(k_xpay_x<P>, g, b, 0, s, a); break;
+    case BL_R_UPDATE:
+        if (a.one) hipLaunchKernelGGL((k_r_update<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_r_update<P>, g, b, 0, s, a);
+        break;
+    case BL_XPAY_X:
+        if (a.one) hipLaunchKernelGGL((k_xpay_x<P, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL(k_xpay_x<P>, g, b, 0, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -194,9 +194,19 @@ struct Cg {
                blas_bytes(S, sloppy, 3, true) + blas_bytes(S, sloppy, 5, true);
     }
 
+    // CGNR, the vectors of the current mask: r = rh in the sloppy precision,
+    // s = M^+ r, gamma = |s|^2
+    wl_status refresh_s()
+    {
+        WL_TRY(convert(S, rl, rh, s));
+        return apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_GAMMA, nullptr));
+    }
+
     // After the FP64 residual rh is fresh: continue (cont) or restart (restart)
     // the sloppy recurrence of the active vectors.  Masks are host vectors.
-    wl_status refresh(const std::vector<int> &cont, const std::vector<int> &restart)
+    // pre: (CGNR) r and s = M^+ r were already formed for a superset of these
+    // vectors in the current sloppy precision, only the restarts remain.
+    wl_status refresh(const std::vector<int> &cont, const std::vector<int> &restart, bool pre = false)
     {
         const int nv = S.nvec;
         std::vector<int> both(nv);
@@ -207,11 +217,12 @@ struct Cg {
             anyr = anyr || restart[v];
         }
         if (!anyc && !anyr) return WL_OK;
-        S.h_active.assign(both.begin(), both.end());
-        WL_TRY(S.upload_active(s));
-        WL_TRY(convert(S, rl, rh, s));
         if (method == M_CGNR) {
-            WL_TRY(apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_GAMMA, nullptr)));
+            if (!pre) {
+                S.h_active.assign(both.begin(), both.end());
+                WL_TRY(S.upload_active(s));
+                WL_TRY(refresh_s());
+            }
             if (anyr) {  // p = s: a fresh search direction
                 S.h_active.assign(restart.begin(), restart.end());
                 WL_TRY(S.upload_active(s));
@@ -220,6 +231,9 @@ struct Cg {
             }
             return WL_OK;
         }
+        S.h_active.assign(both.begin(), both.end());
+        WL_TRY(S.upload_active(s));
+        WL_TRY(convert(S, rl, rh, s));
         if (anyc) {  // keep rhat, p, v, alpha, omega, rho_prev; rho = <rhat, r>
             S.h_active.assign(cont.begin(), cont.end());
             WL_TRY(S.upload_active(s));
@@ -485,18 +499,37 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 break;
             }
             if (anyupd) {
-                for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v] && !restart[v];
+                bool anyrst = false;
+                for (int v = 0; v < nv; ++v) {
+                    S.h_active[v] = upd[v] && !restart[v];
+                    anyrst = anyrst || restart[v];
+                }
                 WL_TRY(S.upload_active(s));
                 Field ac[2] = {cg.xh, cg.xl};
                 WL_TRY(blas(S, BL_ACCUM, cg.sloppy, ac, 2, nullptr, no_red(), s));
-                for (int v = 0; v < nv; ++v) S.h_active[v] = restart[v];
-                WL_TRY(S.upload_active(s));
-                WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+                if (anyrst) {
+                    for (int v = 0; v < nv; ++v) S.h_active[v] = restart[v];
+                    WL_TRY(S.upload_active(s));
+                    WL_TRY(blas(S, BL_ZERO, cg.sloppy, &cg.xl, 1, nullptr, no_red(), s));
+                }
                 for (int v = 0; v < nv; ++v) S.h_active[v] = upd[v];
                 WL_TRY(S.upload_active(s));
                 WL_TRY(cg.residual64());
                 WL_HIP(hipMemcpyAsync(hp, S.scal(SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
-                WL_HIP(hipStreamSynchronize(s));
+                WL_HIP(hipEventRecord(S.rr_ev, s));
+                // CGNR: every updated vector that goes on (continued or restarted)
+                // needs r and s = M^+ r from the new residual; they are queued
+                // before the host has read it, so the GPU works while the host
+                // decides (wasted only for vectors found converged)
+                bool pre = false;
+                double spec_bytes = 0.0;
+                if (method == M_CGNR) {
+                    const double b0 = g_bytes_acc;
+                    WL_TRY(cg.refresh_s());
+                    spec_bytes = g_bytes_acc - b0;
+                    pre = true;
+                }
+                WL_HIP(hipEventSynchronize(S.rr_ev));
                 bool stalled = false;
                 for (int v = 0; v < nv; ++v) {
                     if (!upd[v]) continue;
@@ -537,6 +570,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 // after the FP64 accumulation above, so no vector loses its sloppy progress
                 if ((stalled || anybad) && cg.sloppy != P_F64) {
                     WL_TRY(escalate(anybad ? "non-finite sloppy iterate" : "stagnation", upd));
+                    pre = false;  // r and s are formed anew in the raised precision
                     WL_HIP(hipMemsetAsync(S.bad, 0, sizeof(int32_t) * nv, s));
                     // every vector restarts its search direction in the new precision
                     for (int v = 0; v < nv; ++v)
@@ -551,7 +585,20 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     cont[v] = upd[v] && !done[v] && !restart[v];
                     rst[v] = restart[v] && !done[v];
                 }
-                WL_TRY(cg.refresh(cont, rst));
+                // the byte count keeps only the queued work that was used: none after
+                // an escalation, else that of the vectors that go on (per-vector
+                // bytes are proportional to the sites of the vector's system)
+                if (spec_bytes > 0.0) {
+                    double wu = 0.0, wn = 0.0;
+                    for (int v = 0; v < nv; ++v) {
+                        if (!upd[v]) continue;
+                        const double w = (double)S.systems[S.vec[v].sys].g->geom.Vh;
+                        wu += w;
+                        if (!pre || !(cont[v] || rst[v])) wn += w;
+                    }
+                    if (wu > 0.0) g_bytes_acc -= spec_bytes * wn / wu;
+                }
+                WL_TRY(cg.refresh(cont, rst, pre));
             }
             bool left = false;
             for (int v = 0; v < nv; ++v) {

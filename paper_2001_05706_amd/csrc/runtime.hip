@@ -294,6 +294,7 @@ ExecSet::~ExecSet()
     (void)hipHostFree(h_masks);
     for (auto &e : mask_ev)
         if (e) (void)hipEventDestroy(e);
+    if (rr_ev) (void)hipEventDestroy(rr_ev);
 }
 
 #define WL_ALLOC(ptr, bytes)                                                              \
@@ -345,6 +346,7 @@ wl_status ExecSet::init()
         return set_error(WL_ERR_NOMEM, "cannot allocate pinned host memory");
     }
     for (auto &e : mask_ev) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    WL_HIP(hipEventCreateWithFlags(&rr_ev, hipEventDisableTiming));
     WL_HIP(hipMemcpy(d_active, h_active.data(), sizeof(int32_t) * nvec, hipMemcpyHostToDevice));
     WL_HIP(hipMemset(sc, 0, sizeof(double) * SC_N * nvec));
     WL_HIP(hipMemset(bad, 0, sizeof(int32_t) * nvec));
@@ -356,6 +358,7 @@ wl_status ExecSet::upload_active(hipStream_t s)
 {
     // a ring of pinned staging slots: the upload is ordered on the stream and
     // the host waits only when it reuses a slot whose copy is still pending
+    if (up_valid && up_stream == s && up_active == h_active) return WL_OK;
     const int k = mask_next;
     mask_next = (mask_next + 1) % kMaskRing;
     WL_HIP(hipEventSynchronize(mask_ev[k]));
@@ -363,6 +366,9 @@ wl_status ExecSet::upload_active(hipStream_t s)
     std::copy(h_active.begin(), h_active.end(), h);
     WL_HIP(hipMemcpyAsync(d_active, h, sizeof(int32_t) * nvec, hipMemcpyHostToDevice, s));
     WL_HIP(hipEventRecord(mask_ev[k], s));
+    up_active = h_active;
+    up_stream = s;
+    up_valid = true;
     return WL_OK;
 }
 
@@ -769,6 +775,7 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.s0 = s0;
     a.sc = S.sc;
     a.nvec = S.nvec;
+    a.one = S.nvec == 1;
     a.red = red;
     a.parity = parity;
     a.bcast = bcast;
@@ -809,6 +816,8 @@ wl_status convert(ExecSet &S, const Field &dst, const Field &src, hipStream_t s,
     a.fn[0] = dst.n;
     a.f[1] = src.p;
     a.fn[1] = src.n;
+    a.nvec = S.nvec;
+    a.one = S.nvec == 1;
     a.red = no_red();
     g_bytes_acc += blas_bytes(S, dst.prec, 1, use_active) + blas_bytes(S, src.prec, 1, use_active);
     WL_HIP(launch_convert(dst.prec, src.prec, a, kBlasBlock, s));

@@ -119,12 +119,17 @@ public:
     wl_status layout(int B, const Layout **out);
     int32_t *d_active = nullptr;
     std::vector<int32_t> h_active;
-    // copy h_active to d_active, ordered on the stream (no host synchronisation)
+    // copy h_active to d_active, ordered on the stream (no host synchronisation);
+    // skipped when the same mask was the last one enqueued on the same stream
     wl_status upload_active(hipStream_t s);
     static constexpr int kMaskRing = 16;
     int32_t *h_masks = nullptr;  // pinned staging slots of the mask uploads
     hipEvent_t mask_ev[kMaskRing] = {};
     int mask_next = 0;
+    std::vector<int32_t> up_active;  // the mask last enqueued for d_active
+    hipStream_t up_stream = nullptr; // and its stream
+    bool up_valid = false;
+    hipEvent_t rr_ev = nullptr;      // marks a readback the host waits for while later work runs
 
     // reduction state (per vector unless noted)
     double *partials = nullptr;  // max slots over layouts (B = 64), 3 values each

@@ -18,6 +18,8 @@ struct BlasArgs {
     const double *sc;  // scalar slots of the set (ScSlot), for complex scalars
     int32_t nvec;
     int32_t bcast;     // bit j: field j is one vector shared by every vector of the set
+    int32_t one;       // the set holds one vector (its descriptors are at index 0)
+    int32_t pad_;
     RedSpec red;
 };
 
