@@ -296,6 +296,18 @@ struct Cg {
     }
 };
 
+// Waits for event e by polling it: the readbacks inside the solve loop are a
+// few hundred bytes that the host needs at once, and a blocking wait adds the
+// thread's wake-up to every one of them.
+static wl_status wait_spin(hipEvent_t e)
+{
+    for (;;) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipSuccess) return WL_OK;
+        if (q != hipErrorNotReady) return set_error(WL_ERR_HIP, "waiting for a readback: %s", hipGetErrorString(q));
+    }
+}
+
 static double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -445,7 +457,8 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
             WL_HIP(hipMemcpyAsync(hp, S.hist, sizeof(double) * ExecSet::kHist * nv + sizeof(int32_t) * nv,
                                   hipMemcpyDeviceToHost, s));
             int32_t *hbad = (int32_t *)(hp + (size_t)ExecSet::kHist * nv);
-            WL_HIP(hipStreamSynchronize(s));
+            WL_HIP(hipEventRecord(S.rr_ev, s));
+            WL_TRY(wait_spin(S.rr_ev));
             if (trace) {
                 double sc[ExecSet::SC_N];
                 for (int j = 0; j < ExecSet::SC_N; ++j)
@@ -529,7 +542,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     spec_bytes = g_bytes_acc - b0;
                     pre = true;
                 }
-                WL_HIP(hipEventSynchronize(S.rr_ev));
+                WL_TRY(wait_spin(S.rr_ev));
                 bool stalled = false;
                 for (int v = 0; v < nv; ++v) {
                     if (!upd[v]) continue;
