@@ -194,18 +194,20 @@ struct Cg {
                blas_bytes(S, sloppy, 3, true) + blas_bytes(S, sloppy, 5, true);
     }
 
-    // CGNR, the vectors of the current mask: r = rh in the sloppy precision,
+    // The part of a refresh common to continued and restarted vectors, for the
+    // vectors of the current mask: r = rh in the sloppy precision; CGNR also
     // s = M^+ r, gamma = |s|^2
     wl_status refresh_s()
     {
         WL_TRY(convert(S, rl, rh, s));
+        if (method != M_CGNR) return WL_OK;
         return apply_M(sloppy, recon, true, sv, rl, tl, red_spec(S, RED_GAMMA, nullptr));
     }
 
     // After the FP64 residual rh is fresh: continue (cont) or restart (restart)
     // the sloppy recurrence of the active vectors.  Masks are host vectors.
-    // pre: (CGNR) r and s = M^+ r were already formed for a superset of these
-    // vectors in the current sloppy precision, only the restarts remain.
+    // pre: refresh_s() already ran for a superset of these vectors in the
+    // current sloppy precision.
     wl_status refresh(const std::vector<int> &cont, const std::vector<int> &restart, bool pre = false)
     {
         const int nv = S.nvec;
@@ -231,9 +233,11 @@ struct Cg {
             }
             return WL_OK;
         }
-        S.h_active.assign(both.begin(), both.end());
-        WL_TRY(S.upload_active(s));
-        WL_TRY(convert(S, rl, rh, s));
+        if (!pre) {
+            S.h_active.assign(both.begin(), both.end());
+            WL_TRY(S.upload_active(s));
+            WL_TRY(refresh_s());
+        }
         if (anyc) {  // keep rhat, p, v, alpha, omega, rho_prev; rho = <rhat, r>
             S.h_active.assign(cont.begin(), cont.end());
             WL_TRY(S.upload_active(s));
@@ -530,18 +534,14 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                 WL_TRY(cg.residual64());
                 WL_HIP(hipMemcpyAsync(hp, S.scal(SC_RR), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
                 WL_HIP(hipEventRecord(S.rr_ev, s));
-                // CGNR: every updated vector that goes on (continued or restarted)
-                // needs r and s = M^+ r from the new residual; they are queued
+                // every updated vector that goes on (continued or restarted) needs
+                // r from the new residual, and for CGNR s = M^+ r: they are queued
                 // before the host has read it, so the GPU works while the host
                 // decides (wasted only for vectors found converged)
-                bool pre = false;
-                double spec_bytes = 0.0;
-                if (method == M_CGNR) {
-                    const double b0 = g_bytes_acc;
-                    WL_TRY(cg.refresh_s());
-                    spec_bytes = g_bytes_acc - b0;
-                    pre = true;
-                }
+                const double b0 = g_bytes_acc;
+                WL_TRY(cg.refresh_s());
+                const double spec_bytes = g_bytes_acc - b0;
+                bool pre = true;
                 WL_TRY(wait_spin(S.rr_ev));
                 bool stalled = false;
                 for (int v = 0; v < nv; ++v) {
