@@ -1,22 +1,27 @@
 """Benchmark of the Wilson-Dirac inverter hot path on one MI355X.
 
-Workload: 24^3 x 48 lattice, smooth random links U = exp(i 0.3 H) (plaquette
-~0.61), kappa = 0.1245, one Gaussian source, true residual 1e-10.  A step is
-one complete solve of D psi = eta by mixed-precision even-odd CGNR (sloppy
-storage --sloppy, FP32 arithmetic, FP64 reliable updates and reductions):
-source packing, every D-slash and BLAS kernel of the iteration, the FP64
-residual recomputations, the odd-site reconstruction and the FP64 true
-residual.  Inputs are resident in HBM before the timed region.
+Headline workload (the largest single-GPU configuration): 32^3 x 64 lattice,
+smooth random links U = exp(i 0.3 H) (plaquette ~0.61, seed 1003), kappa =
+0.1248, one Gaussian source (seed 2003), true residual 1e-10.  A step is one
+complete solve of D psi = eta by mixed-precision even-odd CGNR: FP16 storage
+of links (12-real compression) and spinors (per-site FP32 norm), FP32
+arithmetic, FP64 reliable updates, reductions and true residual.  Every
+kernel of the solve is inside the step: source packing, each D-slash and
+BLAS kernel of the iteration, the FP64 residual recomputations, the odd-site
+reconstruction and the FP64 true residual.  Inputs are resident in HBM before
+the timed region.
 
 value  = algorithmic HBM bytes of every kernel of the solve / solve time (GB/s)
-roofline = the dominant kernel (the single-parity hop): algorithmic bytes per
-           launch / mean launch duration (HIP events recorded by each hop's
+roofline = the dominant kernel (the FP16 single-parity hop): algorithmic bytes
+           per launch / mean launch duration (HIP events recorded by each hop's
            dispatch on the solver's stream; the device steady-clock span of
            the same launches reported beside it), against the 8 TB/s HBM peak;
            traffic = the committed rocprofv3 counter reading per launch while
            the hop's sources are unchanged
-cpu_baseline = the FP64 CPU oracle's CGNR solve of the same system, in the same
-           byte model.
+cpu_baseline = the FP64 CPU oracle on a bounded sample of the same workload:
+           CGNR iterations of the same 32^3 x 64 system with every host
+           thread, in the same byte model; single-parity hops with every
+           thread and with one thread beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sloppy f16]
 """
@@ -36,15 +41,16 @@ METRIC = "Dslash GB/s & % HBM peak; CG time to 1e-10 resid, mixed/batched vs FP6
 HBM_PEAK_GBS = 8000.0
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_hop_cg_f16_24c48.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_hop_cg_f16_32c64.md")
 HOP_SOURCES = ("paper_2001_05706_amd/csrc/wl_core.h", "paper_2001_05706_amd/csrc/hop.hip")
 
 
-def measured_traffic(sloppy, recon):
-    """HBM bytes per launch of the FP16 recon-12 hop from the committed rocprofv3
-    counter summary (scaled FETCH_SIZE + WRITE_SIZE), or None when the hop's
-    sources have changed since the counters were taken or another kernel is timed."""
-    if (sloppy, recon) != ("f16", 12) or not os.path.exists(PROFILE):
+def measured_traffic(sloppy, recon, L):
+    """HBM bytes per launch of the FP16 recon-12 hop of the 32^3 x 64 solve from
+    the committed rocprofv3 counter summary (scaled FETCH_SIZE + WRITE_SIZE), or
+    None when the hop's sources have changed since the counters were taken or
+    another kernel or lattice is timed."""
+    if (sloppy, recon, tuple(L)) != ("f16", 12, (32, 32, 32, 64)) or not os.path.exists(PROFILE):
         return None
     rec = None
     for line in open(PROFILE):
@@ -162,29 +168,28 @@ def bench_uneven(w, torch, li, dev, a):
     return r
 
 
-def bench_mixed32(w, torch, li, dev, a):
-    """32^3 x 64, kappa 0.1248: FP16 / BF16 sloppy (recon-12) vs plain FP64."""
-    L = (32, 32, 32, 64)
-    g = w.Gauge(L, _dev(torch, li.near_identity_links(L, 0.3, 1003), dev))
-    e = _dev(torch, li.gaussian_spinor(L, 2003), dev)
+def bench_c2(w, torch, li, dev, a, U, eta):
+    """The 24^3 x 48 workload (kappa 0.1245, seeds 1002/2002): plain FP64 and
+    FP32 solves, and the mixed FP16 solve beside them, CGNR and BiCGStab."""
+    L = (24, 24, 24, 48)
+    g = w.Gauge(L, _dev(torch, U, dev))
+    e = _dev(torch, eta, dev)
     x = torch.zeros_like(e)
     r = {}
-    for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]:
-        def run():
-            x.zero_()
-            return w.wilson_cg(g, e, x, 1, 0.1248, 1e-10, 5000, sl, rc, a.delta)[1][0]
-        try:
-            t, inf = _timed(torch, run, reps=2)
-            r[sl] = {"ms": round(t * 1e3, 2), "iters": inf["iters"], "true_resid": inf["true_resid"],
-                     "GBs": round(inf["gbytes"] / t, 1)}
-        except w.WilsonError as ex:
-            r[sl] = {"error": str(ex)}
-        log("32^3x64 %s: %s" % (sl, r[sl]))
+    for meth, fn in (("cgnr", w.wilson_cg), ("bicgstab", w.wilson_bicgstab)):
+        for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12)]:
+            def run():
+                x.zero_()
+                return fn(g, e, x, 1, 0.1245, 1e-10, 5000, sl, rc, a.delta)[1][0]
+            try:
+                t, inf = _timed(torch, run, reps=3)
+                r["%s_%s" % (meth, sl)] = {"ms": round(t * 1e3, 3), "iters": inf["iters"],
+                                           "updates": inf["reliable_updates"], "true_resid": inf["true_resid"],
+                                           "GBs": round(inf["gbytes"] / t, 1)}
+            except w.WilsonError as ex:
+                r["%s_%s" % (meth, sl)] = {"error": str(ex)}
+            log("24^3x48 %s %s: %s" % (meth, sl, r["%s_%s" % (meth, sl)]))
     g.close()
-    if "ms" in r.get("f64", {}):
-        for sl in ("f32", "f16", "bf16"):
-            if "ms" in r.get(sl, {}):
-                r[sl]["speedup_vs_fp64"] = round(r["f64"]["ms"] / r[sl]["ms"], 3)
     return r
 
 
@@ -212,12 +217,12 @@ def bench_sign(w, torch, li, dev, a):
     return r
 
 
-def bench_clover(w, torch, li, dev, a):
+def bench_clover(w, torch, li, dev, a, U, eta):
     """Wilson-clover e/o CGNR (c_sw 1.0, kappa 0.12) on the 24^3 x 48 workload's
     links and source: FP64 against the mixed FP16 solve, to 1e-10."""
     L = (24, 24, 24, 48)
-    g = w.Gauge(L, _dev(torch, li.near_identity_links(L, 0.3, 1002), dev))
-    eta = _dev(torch, li.gaussian_spinor(L, 2002), dev)
+    g = w.Gauge(L, _dev(torch, U, dev))
+    eta = _dev(torch, eta, dev)
     x = torch.zeros_like(eta)
     r = {}
     for sloppy, recon in (("f64", 18), ("f32", 12), ("f16", 12)):
@@ -259,20 +264,115 @@ def bench_overlap(w, torch, li, dev, a):
     return r
 
 
+def dslash_sets(w, prec, recon, nrhs, vh):
+    """Operand sets rotated by the cold protocol: at least 3, and together more
+    than twice the 256 MB last-level cache, so no launch finds its operands
+    left in a cache by the previous ones (the library allows at most 16)."""
+    link = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[prec] * recon * 8 * vh   # both parities, 4 directions
+    site = {"f64": 192, "f32": 96, "f16": 52, "bf16": 52}[prec]
+    per_set = link + 2 * nrhs * site * vh                                      # links, in, out
+    n = max(3, -(-(2 * 256 * 2 ** 20 + 1) // per_set))
+    return min(n, 16), per_set
+
+
+def bench_dslash(w, torch, li, dev, a, g32, g24, g24b):
+    """Stand-alone single-parity hops (D-slash) in the warm (operands reused,
+    as inside a solver) and cold (rotated operand sets) protocols."""
+    ds = {}
+    stream = torch.cuda.current_stream()
+    cases = [(g32, (32, 32, 32, 64), "f16", 12, 1), (g32, (32, 32, 32, 64), "f32", 12, 1),
+             (g32, (32, 32, 32, 64), "bf16", 12, 1), (g32, (32, 32, 32, 64), "f64", 18, 1),
+             (g24, (24, 24, 24, 48), "f64", 18, 1), (g24, (24, 24, 24, 48), "f64", 12, 1),
+             (g24, (24, 24, 24, 48), "f32", 18, 1), (g24, (24, 24, 24, 48), "f32", 12, 1),
+             (g24, (24, 24, 24, 48), "f16", 12, 1),
+             (g24b, (24, 24, 24, 48), "f32", 12, 12), (g24b, (24, 24, 24, 48), "f16", 12, 12)]
+    for g, L, prec, rc, nrhs in cases:
+        vh = int(np.prod(L)) // 2
+        bps = nrhs * w.wl_hop_bytes_per_site(prec, rc, nrhs)
+        tag = "%dc%d_%s_r%d%s" % (L[0], L[3], prec, rc, "" if nrhs == 1 else "_%drhs" % nrhs)
+        nsets, per_set = dslash_sets(w, prec, rc, nrhs, vh)
+        for ns, name in [(1, "warm"), (nsets, "cold")]:
+            try:
+                sec = w.wl_bench_dslash(g, prec, rc, nrhs, 0, ns, 100 if nrhs == 1 else 20, stream)
+            except w.WilsonError as e:
+                ds["%s_%s" % (tag, name)] = {"error": str(e)}
+                continue
+            gbs = bps * vh / sec / 1e9
+            ds["%s_%s" % (tag, name)] = {"us": round(sec * 1e6, 2), "GBs": round(gbs, 1),
+                                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                         "TFLOPs": round(nrhs * 1320 * vh / sec / 1e12, 3),
+                                         "sets": ns, "rotated_MB": round(ns * per_set / 1e6, 1)}
+            log("dslash %s %s: %s" % (tag, name, ds["%s_%s" % (tag, name)]))
+    return ds
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, L, U, eta, kappa, tol, a):
+    """The FP64 oracle on a bounded sample of the headline workload: a capped
+    number of CGNR iterations with every host thread (setup and true residual
+    included), and single-parity hops with every thread and with one."""
+    import oracle
+
+    vh = int(np.prod(L)) // 2
+    nthreads = oracle.num_threads()
+    t0 = time.perf_counter()
+    _, _, it, _ = oracle.cg_eo(L, U, eta, kappa, tol, maxiter=a.cpu_iters)
+    dt = time.perf_counter() - t0
+    n_it = int(it[0])
+    cg_bytes = n_it * cg_iteration_bytes(w, "f64", 18, vh)
+    hop_b = w.wl_hop_bytes_per_site("f64", 18, 1) * vh
+    t0 = time.perf_counter()
+    for _ in range(2):
+        oracle.hop(L, U, eta, out_parity=0)
+    hop_all = (time.perf_counter() - t0) / 2
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.hop(L, U, eta, out_parity=0)
+        hop_one = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(nthreads)
+    r = {
+        "value": round(cg_bytes / dt / 1e9, 3),
+        "unit": "GB/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": "FP64 oracle e/o CGNR on the same %dx%dx%dx%d system (kappa %g), capped at %d iterations "
+                  "(%.1f s incl. setup; FP64 recon-18 byte model of the iterations only), %d threads"
+                  % (L + (kappa, n_it, dt, nthreads)),
+        "cpu_model": cpu_model(),
+        "ms_per_cg_iteration": round(dt * 1e3 / max(n_it, 1), 1),
+        "dslash_all_threads": {"ms": round(hop_all * 1e3, 1), "GBs": round(hop_b / hop_all / 1e9, 3),
+                               "GFLOPs": round(1320 * vh / hop_all / 1e9, 2), "threads": nthreads},
+        "dslash_one_thread": {"ms": round(hop_one * 1e3, 1), "GBs": round(hop_b / hop_one / 1e9, 3),
+                              "GFLOPs": round(1320 * vh / hop_one / 1e9, 2), "threads": 1},
+    }
+    log("cpu oracle: %s" % r)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sloppy", default="f16", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--recon", type=int, default=12)
     ap.add_argument("--delta", type=float, default=0.1)
-    ap.add_argument("--lattice", default="24,24,24,48")
-    ap.add_argument("--cpu-iters", type=int, default=100,
-                    help="cap on the oracle CG iterations timed for the CPU baseline (the solve converges in ~65)")
+    ap.add_argument("--cpu-iters", type=int, default=6,
+                    help="cap on the oracle CG iterations timed for the CPU baseline (a bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip every side measurement")
-    ap.add_argument("--extras", default="cg,dslash,batch,uneven,mixed32,sign,overlap,clover",
+    ap.add_argument("--extras", default="cg,c2,dslash,batch,uneven,sign,overlap,clover",
                     help="side measurements outside the timed region (comma list)")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -286,14 +386,13 @@ def main():
 
     w.lib()
     dev = torch.device("cuda:0")
-    L = tuple(int(v) for v in a.lattice.split(","))
-    V = L[0] * L[1] * L[2] * L[3]
-    vh = V // 2
-    kappa, tol, maxiter = 0.1245, 1e-10, 5000
+    L = (32, 32, 32, 64)
+    vh = int(np.prod(L)) // 2
+    kappa, tol, maxiter = 0.1248, 1e-10, 5000
 
     t0 = time.time()
-    U = li.near_identity_links(L, 0.3, 1002)
-    eta = li.gaussian_spinor(L, 2002)
+    U = li.near_identity_links(L, 0.3, 1003)
+    eta = li.gaussian_spinor(L, 2003)
     log("inputs generated in %.1f s" % (time.time() - t0))
     Ud = torch.from_numpy(U.view(np.float64)).to(dev)
     etad = torch.from_numpy(eta.view(np.float64)).to(dev)
@@ -345,6 +444,9 @@ def main():
     log("hop launches %d, mean launch %.2f us (HIP events; span %.2f us on the steady clock), %.1f GB/s" %
         (n_hop, hop_event_us, hop_span_us, achieved))
 
+    storage = {"f64": "f64 links (recon-%d) and spinors", "f32": "f32 links (recon-%d) and spinors",
+               "f16": "f16 links (recon-%d), f16 spinors with a per-site f32 norm",
+               "bf16": "bf16 links (recon-%d), bf16 spinors with a per-site f32 norm"}[a.sloppy] % a.recon
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -356,15 +458,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if a.sloppy == "f64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": "e/o CGNR solve to 1e-10 true residual, %dx%dx%dx%d, eps=0.3 links, kappa=%g, 1 Gaussian rhs"
-                        % (L + (kappa,)),
+            "workload": "mixed-precision e/o CGNR solve to a 1e-10 true residual, %dx%dx%dx%d, eps=0.3 links "
+                        "(seed 1003), kappa=%g, 1 Gaussian rhs (seed 2003)" % (L + (kappa,)),
             "lattice": list(L),
+            "storage": storage,
+            "arithmetic": "f32 iterations; f64 reliable updates, reductions and true residual"
+                          if a.sloppy != "f64" else "f64",
             "sloppy_storage": a.sloppy,
             "recon": a.recon,
-            "arithmetic": "f32 sloppy, f64 reliable updates / reductions / true residual",
             "delta": a.delta,
             "iters": infos[0]["iters"],
             "reliable_updates": infos[0]["reliable_updates"],
@@ -377,86 +481,66 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(a.sloppy, a.recon),
+            "traffic": measured_traffic(a.sloppy, a.recon, L),
             "mean_launch_us": round(hop_event_us, 3),
             "mean_span_us_clock": round(hop_span_us, 3),
             "launches": n_hop,
+            "bytes_per_launch": round(hop_gb * 1e9 / max(n_hop, 1)),
         },
     }
 
     extras = set() if a.no_extra else set(a.extras.split(","))
     if "cg" in extras:
-        # plain FP64 GPU solver (recon 18) and other sloppy precisions, same workload
+        # the plain FP64 GPU solver (recon 18) and the other storage formats on the
+        # same workload, CGNR and BiCGStab
         cmp = {}
-        for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]:
-            try:
-                solve(sl, rc)
-                torch.cuda.synchronize()
-                ts = []
-                for _ in range(3):
-                    tt = time.perf_counter()
-                    inf = solve(sl, rc)
-                    torch.cuda.synchronize()
-                    ts.append(time.perf_counter() - tt)
-            except w.WilsonError as e:
-                cmp[sl] = {"error": str(e)}
-                log("solve %s failed: %s" % (sl, e))
-                continue
-            cmp[sl] = {"ms": round(min(ts) * 1e3, 3), "iters": inf["iters"], "updates": inf["reliable_updates"],
-                       "true_resid": inf["true_resid"]}
-            log("solve %s: %.2f ms, %d iters, resid %.2e" % (sl, min(ts) * 1e3, inf["iters"], inf["true_resid"]))
+        for meth, fn in (("cgnr", w.wilson_cg), ("bicgstab", w.wilson_bicgstab)):
+            for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)]:
+                def run():
+                    x.zero_()
+                    return fn(g, etad, x, 1, kappa, tol, maxiter, sl, rc, a.delta, stream=stream)[1][0]
+                try:
+                    t, inf = _timed(torch, run, reps=3)
+                except w.WilsonError as e:
+                    cmp["%s_%s" % (meth, sl)] = {"error": str(e)}
+                    log("%s %s failed: %s" % (meth, sl, e))
+                    continue
+                cmp["%s_%s" % (meth, sl)] = {"ms": round(t * 1e3, 3), "iters": inf["iters"],
+                                             "updates": inf["reliable_updates"],
+                                             "escalations": inf["precision_escalations"],
+                                             "true_resid": inf["true_resid"], "GBs": round(inf["gbytes"] / t, 1)}
+                log("%s %s: %s" % (meth, sl, cmp["%s_%s" % (meth, sl)]))
         out["cg_time_to_1e-10_ms"] = cmp
-        # BiCGStab on the Schur system, same workload and stopping rule
-        bic = {}
-        for sl, rc in [("f64", 18), ("f32", 12), ("f16", 12)]:
-            def run_b():
-                x.zero_()
-                return w.wilson_bicgstab(g, etad, x, 1, kappa, tol, maxiter, sl, rc, a.delta, stream=stream)[1][0]
-            try:
-                tb_, ib_ = _timed(torch, run_b)
-                bic[sl] = {"ms": round(tb_ * 1e3, 3), "iters": ib_["iters"], "updates": ib_["reliable_updates"],
-                           "true_resid": ib_["true_resid"]}
-            except w.WilsonError as e:
-                bic[sl] = {"error": str(e)}
-            log("bicgstab %s: %s" % (sl, bic[sl]))
-        out["bicgstab_time_to_1e-10_ms"] = bic
-        if "ms" in cmp.get("f64", {}) and "ms" in cmp.get(a.sloppy, {}):
-            out["cg_speedup_vs_fp64"] = round(cmp["f64"]["ms"] / cmp[a.sloppy]["ms"], 3)
-    if "dslash" in extras:
-        # stand-alone D-slash (hop only), warm and cold operand protocols
-        ds = {}
-        for prec, rc in [("f64", 18), ("f32", 12), ("f16", 12)]:
-            bps = w.wl_hop_bytes_per_site(prec, rc, 1)
-            for nsets, name in [(1, "warm"), (4, "cold")]:
-                sec = w.wl_bench_dslash(g, prec, rc, 1, 0, nsets, 100, stream)
-                gbs = bps * vh / sec / 1e9
-                ds["%s_r%d_%s" % (prec, rc, name)] = {"us": round(sec * 1e6, 2), "GBs": round(gbs, 1),
-                                                     "TFLOPs": round(1320 * vh / sec / 1e12, 3)}
-                log("dslash %s r%d %s: %.2f us, %.1f GB/s" % (prec, rc, name, sec * 1e6, gbs))
-        try:
-            g12 = w.Gauge(L, Ud)
-            sec = w.wl_bench_dslash(g12, "f32", 12, 12, 0, 1, 20, stream)
-            bps = w.wl_hop_bytes_per_site("f32", 12, 12)
-            ds["f32_r12_12rhs_warm"] = {"us": round(sec * 1e6, 2), "GBs": round(12 * bps * vh / sec / 1e9, 1),
-                                        "TFLOPs": round(12 * 1320 * vh / sec / 1e12, 3)}
-            log("dslash f32 r12 x12 rhs: %.2f us, %.1f GB/s" % (sec * 1e6, 12 * bps * vh / sec / 1e9))
-            g12.close()
-        except w.WilsonError as e:
-            ds["f32_r12_12rhs_warm"] = {"error": str(e)}
-        out["dslash"] = ds
+        if "ms" in cmp.get("cgnr_f64", {}) and "ms" in cmp.get("cgnr_" + a.sloppy, {}):
+            out["cg_speedup_vs_fp64"] = round(cmp["cgnr_f64"]["ms"] / cmp["cgnr_" + a.sloppy]["ms"], 3)
     side = {}
+    U24 = eta24 = None
+    if extras & {"c2", "clover", "dslash"}:
+        L24 = (24, 24, 24, 48)
+        U24 = li.near_identity_links(L24, 0.3, 1002)
+        eta24 = li.gaussian_spinor(L24, 2002)
+    if "dslash" in extras:
+        def run_ds():
+            g24 = w.Gauge((24, 24, 24, 48), _dev(torch, U24, dev))
+            g24b = w.Gauge((24, 24, 24, 48), _dev(torch, U24, dev))
+            try:
+                return bench_dslash(w, torch, li, dev, a, g, g24, g24b)
+            finally:
+                g24.close()
+                g24b.close()
+        out["dslash"] = _guard(run_ds)
+    if "c2" in extras:
+        side["solves_24c48"] = _guard(lambda: bench_c2(w, torch, li, dev, a, U24, eta24))
     if "batch" in extras:
         side["batched_12_point_sources"] = _guard(lambda: bench_batch12(w, torch, li, dev, a))
     if "uneven" in extras:
         side["uneven_batch_16_lattices"] = _guard(lambda: bench_uneven(w, torch, li, dev, a))
-    if "mixed32" in extras:
-        side["mixed_32c64"] = _guard(lambda: bench_mixed32(w, torch, li, dev, a))
     if "sign" in extras:
         side["sign_function_16c32"] = _guard(lambda: bench_sign(w, torch, li, dev, a))
     if "overlap" in extras:
         side["overlap_solve_16c32"] = _guard(lambda: bench_overlap(w, torch, li, dev, a))
     if "clover" in extras:
-        side["clover_cg_24c48"] = _guard(lambda: bench_clover(w, torch, li, dev, a))
+        side["clover_cg_24c48"] = _guard(lambda: bench_clover(w, torch, li, dev, a, U24, eta24))
     if side:
         out["configs"] = side
 
@@ -467,26 +551,10 @@ def main():
     out["copy_reference"] = {"bytes_each_way": copy_bytes, "GBs": round(2 * copy_bytes / sec / 1e9, 1)}
     log("copy %d MiB: %.1f GB/s (read + write)" % (copy_bytes >> 20, out["copy_reference"]["GBs"]))
 
-    if not a.no_cpu:
-        import oracle
-
-        t0 = time.perf_counter()
-        _, _, it, _ = oracle.cg_eo(L, U, eta, kappa, tol, maxiter=a.cpu_iters)
-        dt = time.perf_counter() - t0
-        n_it = int(it[0])
-        cpu_bytes = n_it * cg_iteration_bytes(w, "f64", 18, vh)
-        out["cpu_baseline"] = {
-            "value": round(cpu_bytes / dt / 1e9, 3),
-            "unit": "GB/s",
-            "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "FP64 oracle e/o CGNR solve of the same %dx%dx%dx%d system to 1e-10, %d iterations "
-                      "(%.1f s incl. setup and true residual), FP64 recon-18 byte model" % (L + (n_it, dt)),
-            "ms_per_iteration": round(dt * 1e3 / max(n_it, 1), 1),
-        }
-        log("cpu oracle: %.1f s for %d iterations" % (dt, n_it))
-
     g.close()
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, L, U, eta, kappa, tol, a)
+
     print(json.dumps(out), flush=True)
     return 0
 

@@ -35,7 +35,14 @@
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
  * All device work of a call is enqueued on it.  wilson_dslash returns without
  * synchronising; solver and sign-function calls synchronise the stream before
- * they return because they fill host-side results.
+ * they return because they fill host-side results.  Calls on one handle share
+ * its packed fields and workspaces: the caller orders them, either by issuing
+ * them on one stream or by making a later call's stream wait for the earlier
+ * call's work (hipStreamWaitEvent); a call that returned after synchronising
+ * its stream needs nothing more.  The packed copies of the links and of the
+ * clover term are the exception: each is built once, on the stream of the
+ * call that first needs it, and a call on another stream waits for that build
+ * by itself.
  *
  * Errors: every entry point returns a wl_status and never aborts or throws.
  * Arguments are validated before any device work; wl_last_error() returns a

@@ -119,6 +119,14 @@ def num_threads() -> int:
     return int(_load().or_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (OpenMP's own setter,
+    reached through the library's handle; used to time the oracle on one core)."""
+    fn = _load().omp_set_num_threads
+    fn.argtypes = [ctypes.c_int]
+    fn(int(n))
+
+
 def gamma(mu: int) -> np.ndarray:
     """The oracle's gamma matrix: mu = 0..3 (x, y, z, t), 4 = gamma_5."""
     out = np.zeros((4, 4), dtype=np.complex128)

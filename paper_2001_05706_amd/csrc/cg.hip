@@ -38,6 +38,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 
 #include "wl_host.h"
 
@@ -264,8 +265,12 @@ struct Cg {
             if (method == M_CGNR) WL_TRY(hist_finalize(S, k, s));
             return WL_OK;
         }
+        // the coefficient tables are cached by content, so their addresses name
+        // the systems' kappas: a chunk captured for other kappas is not reused
+        char coefs[64];
+        snprintf(coefs, sizeof(coefs), "/%p/%p", (const void *)c_plain, (const void *)c_M);
         const std::string key = "cg/" + std::to_string(method) + "/" + std::to_string(k) + "/" +
-                                std::to_string(sloppy) + "/" + std::to_string(recon);
+                                std::to_string(sloppy) + "/" + std::to_string(recon) + coefs;
         auto it = S.graphs.find(key);
         if (it == S.graphs.end()) {
             const SysDesc *tab = nullptr;  // packed links and tables exist before capture
@@ -302,13 +307,28 @@ struct Cg {
 
 // Waits for event e by polling it: the readbacks inside the solve loop are a
 // few hundred bytes that the host needs at once, and a blocking wait adds the
-// thread's wake-up to every one of them.
+// thread's wake-up to every one of them.  After the first few thousand polls
+// the thread yields between polls, and a wait longer than WL_WAIT_TIMEOUT_S
+// seconds (default 600) returns an error instead of spinning on a GPU that
+// no longer answers.
 static wl_status wait_spin(hipEvent_t e)
 {
-    for (;;) {
+    static const double limit = [] {
+        const char *v = getenv("WL_WAIT_TIMEOUT_S");
+        const double t = v ? atof(v) : 0.0;
+        return t > 0.0 ? t : 600.0;
+    }();
+    const auto t0 = std::chrono::steady_clock::now();
+    for (long n = 0;; ++n) {
         const hipError_t q = hipEventQuery(e);
         if (q == hipSuccess) return WL_OK;
         if (q != hipErrorNotReady) return set_error(WL_ERR_HIP, "waiting for a readback: %s", hipGetErrorString(q));
+        if (n >= 4096) {
+            std::this_thread::yield();
+            if ((n & 1023) == 0 &&
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > limit)
+                return set_error(WL_ERR_HIP, "a readback did not complete within %.0f s", limit);
+        }
     }
 }
 

@@ -201,23 +201,39 @@ wl_gauge_s::~wl_gauge_s()
     (void)hipFree(U);
     for (auto &a : packed)
         for (auto &p : a) (void)hipFree(p);
-    for (auto &c : clovers)
+    for (auto &a : packed_ev)
+        for (auto &e : a)
+            if (e) (void)hipEventDestroy(e);
+    for (auto &c : clovers) {
         for (int k = 0; k < 3; ++k) {
             (void)hipFree(c.A[k]);
             (void)hipFree(c.Ainv[k]);
         }
+        if (c.built_ev) (void)hipEventDestroy(c.built_ev);
+    }
 }
 
 namespace wl {
 
+// Work on stream s that reads data built on stream `on` (behind event ev) waits
+// for it; nothing to do on the same stream, or inside a capture (data used in
+// a capture is built before it starts).
+static wl_status order_after(hipStream_t on, hipEvent_t ev, hipStream_t s)
+{
+    if (ev && on != s && !capturing(s)) WL_HIP(hipStreamWaitEvent(s, ev, 0));
+    return WL_OK;
+}
+
 wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const void **out)
 {
     if (!prec_recon_ok(prec, recon)) return set_error(WL_ERR_PREC, "unsupported precision %d / recon %d", prec, recon);
-    void *&p = g->packed[prec][recon == 12 ? 1 : 0];
+    const int r = recon == 12 ? 1 : 0;
+    void *&p = g->packed[prec][r];
     if (!p && capturing(s))  // packing would record a memset node into the caller's graph
         return set_error(WL_ERR_HIP, "links of precision %d / recon %d first needed inside a graph capture", prec, recon);
     if (!p) {
         const size_t bytes = (size_t)2 * 4 * link_nchunks(prec, recon) * g->geom.gstride * link_chunk_bytes(prec, recon);
+        if (!g->packed_ev[prec][r]) WL_HIP(hipEventCreateWithFlags(&g->packed_ev[prec][r], hipEventDisableTiming));
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             p = nullptr;
@@ -225,6 +241,10 @@ wl_status gauge_packed(wl_gauge g, int prec, int recon, hipStream_t s, const voi
         }
         WL_HIP(hipMemsetAsync(p, 0, bytes, s));
         WL_HIP(launch_pack_gauge(prec, recon, g->U, p, g->geom, s));
+        WL_HIP(hipEventRecord(g->packed_ev[prec][r], s));
+        g->packed_on[prec][r] = s;
+    } else {
+        WL_TRY(order_after(g->packed_on[prec][r], g->packed_ev[prec][r], s));
     }
     *out = p;
     return WL_OK;
@@ -235,12 +255,14 @@ wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const voi
     const int k = prec == P_F64 ? 0 : prec == P_F32 ? 1 : 2;
     for (auto &c : g->clovers)
         if (c.kc == kc) {
+            WL_TRY(order_after(c.built_on, c.built_ev, s));
             *A = c.A[k];
             *Ainv = c.Ainv[k];
             return WL_OK;
         }
     if (capturing(s)) return set_error(WL_ERR_HIP, "clover term first needed inside a graph capture");
-    wl_gauge_s::Clover c{kc, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    wl_gauge_s::Clover c{kc, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, s, nullptr};
+    WL_HIP(hipEventCreateWithFlags(&c.built_ev, hipEventDisableTiming));
     const size_t per = (size_t)2 * g->geom.stride * 72;  // reals of one field, both parities
     bool ok = true;
     for (int j = 0; j < 3 && ok; ++j) {
@@ -254,11 +276,13 @@ wl_status gauge_clover(wl_gauge g, double kc, int prec, hipStream_t s, const voi
             (void)hipFree(c.A[j]);
             (void)hipFree(c.Ainv[j]);
         }
+        (void)hipEventDestroy(c.built_ev);
         return set_error(WL_ERR_NOMEM, "cannot allocate the clover term");
     }
     g->clovers.push_back(c);
     WL_HIP(launch_clover_build(g->U, g->geom, kc, c.A[0], c.A[1], c.A[2], s));
     WL_HIP(launch_clover_invert(g->geom, c.A[0], c.Ainv[0], c.Ainv[1], c.Ainv[2], s));
+    WL_HIP(hipEventRecord(c.built_ev, s));
     *A = c.A[k];
     *Ainv = c.Ainv[k];
     return WL_OK;

@@ -55,11 +55,17 @@ struct wl_gauge_s {
     int device = 0;
     double *U = nullptr;       // canonical FP64 copy (device)
     void *packed[4][2] = {};   // [prec][recon == 12]
+    // the stream each packed copy was built on and an event recorded behind the
+    // packing kernel: a call on another stream waits for it before reading
+    hipStream_t packed_on[4][2] = {};
+    hipEvent_t packed_ev[4][2] = {};
     // clover term A and A^{-1} per value of kappa * c_sw, FP64 [0], FP32 [1], FP16 [2]
     struct Clover {
         double kc;
         void *A[3];
         void *Ainv[3];
+        hipStream_t built_on;
+        hipEvent_t built_ev;
     };
     std::vector<Clover> clovers;
     ~wl_gauge_s();

@@ -184,3 +184,74 @@ def test_repeated_solves_across_streams():
     g.close()
     for xo in outs[1:]:
         assert np.array_equal(xo, outs[0])
+
+
+def test_one_handle_two_kappas_with_graphs():
+    """A handle solved at one kappa and then at another replays no iteration
+    chunk captured for the first: the second solve takes the iterations and
+    reaches the residual of a solve on a fresh handle, and its solution agrees
+    with that one to round-off."""
+    w = need_gpu()
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2002, nrhs=2)
+    for sloppy, method in (("f16", w.wilson_cg), ("f32", w.wilson_bicgstab)):
+        g = w.Gauge(L, to_dev(U))
+        d = to_dev(eta)
+        x = to_dev(np.zeros_like(eta))
+        method(g, d, x, 2, 0.12, 1e-10, 2000, sloppy, 12, 0.1)
+        x.zero_()
+        _, info = method(g, d, x, 2, 0.1245, 1e-10, 2000, sloppy, 12, 0.1)
+        xa = from_dev(x, eta.shape)
+        g.close()
+        g2 = w.Gauge(L, to_dev(U))
+        x2 = to_dev(np.zeros_like(eta))
+        _, info2 = method(g2, d, x2, 2, 0.1245, 1e-10, 2000, sloppy, 12, 0.1)
+        xb = from_dev(x2, eta.shape)
+        g2.close()
+        tr = true_resid(L, U, eta, xa, 0.1245)
+        assert tr.max() <= 1e-10, (sloppy, tr)
+        for r in range(2):
+            assert info[r]["iters"] == info2[r]["iters"], (sloppy, info, info2)
+            assert info[r]["reliable_updates"] == info2[r]["reliable_updates"]
+        assert rel(xa, xb) <= 1e-12, (sloppy, rel(xa, xb))
+
+
+@pytest.mark.parametrize("method", ["cgnr", "bicgstab", "multi"])
+def test_graph_replay_matches_eager(method, monkeypatch):
+    """The iteration chunks replayed from captured graphs and the same chunks
+    launched one kernel at a time (WL_GRAPHS=0) give bit-identical solutions,
+    iteration counts and update schedules: the graph path adds no race."""
+    w = need_gpu()
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2003, nrhs=3)
+    eta[2] *= 1e-3  # converges at another iteration: the mask changes inside the solve
+
+    def run():
+        g = w.Gauge(L, to_dev(U))
+        x = to_dev(np.zeros_like(eta))
+        if method == "multi":
+            L2 = (4, 4, 4, 8)
+            U2 = li.near_identity_links(L2, 0.3, 3001)
+            e2 = li.gaussian_spinor(L2, 4001, nrhs=2)
+            g2 = w.Gauge(L2, to_dev(U2))
+            x2 = to_dev(np.zeros_like(e2))
+            _, info = w.wilson_cg_multi([g, g2], [to_dev(eta), to_dev(e2)], [x, x2], [3, 2], [0.1245, 0.124],
+                                        1e-10, 2000, "f16", 12, 0.1)
+            out = np.concatenate([from_dev(x, eta.shape).ravel(), from_dev(x2, e2.shape).ravel()])
+            g2.close()
+        else:
+            fn = w.wilson_cg if method == "cgnr" else w.wilson_bicgstab
+            _, info = fn(g, to_dev(eta), x, 3, 0.1245, 1e-10, 2000, "f16", 12, 0.1)
+            out = from_dev(x, eta.shape)
+        g.close()
+        return out, [(i["iters"], i["reliable_updates"], i["converged"]) for i in info]
+
+    monkeypatch.delenv("WL_GRAPHS", raising=False)
+    xg, ig = run()
+    monkeypatch.setenv("WL_GRAPHS", "0")
+    xe, ie = run()
+    assert ig == ie, (ig, ie)
+    assert all(c for _, _, c in ig)
+    assert np.array_equal(xg, xe)
