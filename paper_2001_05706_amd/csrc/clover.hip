@@ -152,8 +152,7 @@ __device__ void store_block(void *A64, void *A32, void *A16, const SysDesc &d, i
     char *f16 = (char *)clover_parity<P_F16>(A16, par, d.stride);
     for (int k = 0; k < 9; ++k) {
         const int u = 9 * b + k;
-        const uint2 w{pack2<P_F16>((float)m[4 * k], (float)m[4 * k + 1]),
-                      pack2<P_F16>((float)m[4 * k + 2], (float)m[4 * k + 3])};
+        const uint2 w{pack2_d<P_F16>(m[4 * k], m[4 * k + 1]), pack2_d<P_F16>(m[4 * k + 2], m[4 * k + 3])};
         *(uint2 *)(f16 + ((size_t)(u >> 1) * d.stride + cb) * 16 + (u & 1) * 8) = w;
     }
 }

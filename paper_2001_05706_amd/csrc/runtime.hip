@@ -947,6 +947,8 @@ wl_status wl_gauge_create(const wl_geom *geom, const double *U_dev, void *stream
         V *= (size_t)L;
     }
     if (V / 2 > (size_t)(1 << 26)) return set_error(WL_ERR_GEOM, "lattice of %zu sites is too large", V);
+    for (int mu = 0; mu < 4; ++mu)
+        if (geom->L[mu] > (1 << 16)) return set_error(WL_ERR_GEOM, "L[%d] = %d exceeds 65536", mu, geom->L[mu]);
     if (geom->antiperiodic_t != 0 && geom->antiperiodic_t != 1)
         return set_error(WL_ERR_ARG, "antiperiodic_t must be 0 or 1");
     const size_t bytes = V * 4 * 18 * sizeof(double);
@@ -962,6 +964,7 @@ wl_status wl_gauge_create(const wl_geom *geom, const double *U_dev, void *stream
     d.stride = padded(d.Vh);
     d.gstride = d.stride;
     d.tap = geom->antiperiodic_t;
+    set_divisors(d);
     WL_HIP(hipGetDevice(&g->device));
     if (hipMalloc((void **)&g->U, bytes) != hipSuccess) {
         (void)hipGetLastError();

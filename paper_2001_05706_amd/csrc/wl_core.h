@@ -110,6 +110,22 @@ template <int P> WL_HD uint32_t pack2(float lo, float hi)
     return a | (b << 16);
 }
 
+// the FP16 number nearest to an FP64 one (a single rounding, to nearest even)
+WL_HD uint16_t double_to_f16(double d)
+{
+    union { uint16_t u; _Float16 f; } c;
+    c.f = (_Float16)d;
+    return c.u;
+}
+
+// Two FP64 values (links, clover entries) in half precision: FP16 rounds each
+// once from FP64; BF16 rounds to FP32, then to BF16 on its bits.
+template <int P> WL_HD uint32_t pack2_d(double lo, double hi)
+{
+    if constexpr (P == P_F16) return (uint32_t)double_to_f16(lo) | ((uint32_t)double_to_f16(hi) << 16);
+    return pack2<P>((float)lo, (float)hi);
+}
+
 // ------------------------------------------------------------------ storage traits
 
 template <int P> struct SpinorFmt;
@@ -154,69 +170,93 @@ typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef uint32_t nt_u2 __attribute__((ext_vector_type(2)));
 typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
 
+// Field data lives in global memory: on the device the access helpers use
+// pointers in the global address space, so that every load and store is a
+// global instruction (a generic pointer read from a descriptor would compile to
+// flat instructions, which also occupy the LDS counter the waits test).
 #if defined(__HIP_DEVICE_COMPILE__)
-#define WL_NT_LOAD(VT, p) __builtin_nontemporal_load((const VT *)(p))
-#define WL_NT_STORE(VT, v, p) __builtin_nontemporal_store((v), (VT *)(p))
+#define WL_G __attribute__((address_space(1)))
+#define WL_NT_LOAD(VT, p) __builtin_nontemporal_load((const WL_G VT *)(p))
+#define WL_NT_STORE(VT, v, p) __builtin_nontemporal_store((v), (WL_G VT *)(p))
 #else
+#define WL_G
 #define WL_NT_LOAD(VT, p) (*(const VT *)(p))
 #define WL_NT_STORE(VT, v, p) (*(VT *)(p) = (v))
 #endif
 
 // stores of written-once data (a kernel's output field), plain or with the
 // non-temporal hint
-template <bool NT> WL_HD void st_out(double2 *p, double2 v)
+template <bool NT> WL_HD void st_out(WL_G double2 *p, double2 v)
 {
     if constexpr (NT) WL_NT_STORE(nt_d2, (nt_d2{v.x, v.y}), p);
     else *p = v;
 }
-template <bool NT> WL_HD void st_out(float4 *p, float4 v)
+template <bool NT> WL_HD void st_out(WL_G float4 *p, float4 v)
 {
     if constexpr (NT) WL_NT_STORE(nt_f4, (nt_f4{v.x, v.y, v.z, v.w}), p);
     else *p = v;
 }
-template <bool NT> WL_HD void st_out(uint4 *p, uint4 v)
+template <bool NT> WL_HD void st_out(WL_G uint4 *p, uint4 v)
 {
     if constexpr (NT) WL_NT_STORE(nt_u4, (nt_u4{v.x, v.y, v.z, v.w}), p);
     else *p = v;
 }
-template <bool NT> WL_HD void st_out(float *p, float v)
+template <bool NT> WL_HD void st_out(WL_G float *p, float v)
 {
     if constexpr (NT) WL_NT_STORE(float, v, p);
     else *p = v;
 }
 
-WL_HD double2 ld_stream(const double2 *p)
+WL_HD double2 ld_stream(const WL_G double2 *p)
 {
     const nt_d2 v = WL_NT_LOAD(nt_d2, p);
     return double2{v.x, v.y};
 }
-WL_HD float2 ld_stream(const float2 *p)
+WL_HD float2 ld_stream(const WL_G float2 *p)
 {
     const nt_f2 v = WL_NT_LOAD(nt_f2, p);
     return float2{v.x, v.y};
 }
-WL_HD float4 ld_stream(const float4 *p)
+WL_HD float4 ld_stream(const WL_G float4 *p)
 {
     const nt_f4 v = WL_NT_LOAD(nt_f4, p);
     return float4{v.x, v.y, v.z, v.w};
 }
-WL_HD uint2 ld_stream(const uint2 *p)
+WL_HD uint2 ld_stream(const WL_G uint2 *p)
 {
     const nt_u2 v = WL_NT_LOAD(nt_u2, p);
     return uint2{v.x, v.y};
 }
 
-// Element `cb` of chunk row `c`: a uniform row base (scalar registers) plus a
-// 32-bit lane offset, so each load costs one vector register of address.
-template <class CH> WL_HD const CH *row_elem(const void *base, int c, int stride, int cb)
+// The address of a row base held in scalar registers.  `base` must be the
+// same in every lane of the wave (every kernel here takes its field bases from
+// per-block or per-wave descriptors); the base is read from the first lane, so
+// the compiler keeps one scalar base per row instead of folding the lane
+// offset into a 64-bit vector address shared by the rows.
+WL_HD uintptr_t uniform_addr(uintptr_t a)
 {
-    const char *row = (const char *)base + (size_t)c * (size_t)stride * sizeof(CH);
-    return (const CH *)(row + (uint32_t)((uint32_t)cb * (uint32_t)sizeof(CH)));
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return ((uintptr_t)hi << 32) | lo;
+#else
+    return a;
+#endif
 }
-template <class CH> WL_HD CH *row_elem(void *base, int c, int stride, int cb)
+
+// Element `cb` of chunk row `c`: a uniform row base (scalar registers) plus a
+// 32-bit lane offset, so each load is one global instruction with a scalar base
+// and a 32-bit vector offset, and needs no 64-bit vector address arithmetic.
+template <class CH> WL_HD const WL_G CH *row_elem(const void *base, int c, int stride, int cb)
 {
-    char *row = (char *)base + (size_t)c * (size_t)stride * sizeof(CH);
-    return (CH *)(row + (uint32_t)((uint32_t)cb * (uint32_t)sizeof(CH)));
+    const WL_G char *row =
+        (const WL_G char *)uniform_addr((uintptr_t)base + (size_t)c * (size_t)stride * sizeof(CH));
+    return (const WL_G CH *)(row + (uint32_t)((uint32_t)cb * (uint32_t)sizeof(CH)));
+}
+template <class CH> WL_HD WL_G CH *row_elem(void *base, int c, int stride, int cb)
+{
+    WL_G char *row = (WL_G char *)uniform_addr((uintptr_t)base + (size_t)c * (size_t)stride * sizeof(CH));
+    return (WL_G CH *)(row + (uint32_t)((uint32_t)cb * (uint32_t)sizeof(CH)));
 }
 
 // 24 reals of one site of one vector.  base points at chunk 0 of the vector.
@@ -313,7 +353,11 @@ WL_HD void store_spinor(void *base, float *norm, int stride, int cb, const typen
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
-        // a zero site stores zeros and a zero norm (point sources are zero almost everywhere)
+        // a zero site stores zeros and a zero norm (point sources are zero almost everywhere).
+        // Stored value: v * inv with inv = 1/m correctly rounded; for FP16 the multiply
+        // and the conversion compile to one mixed-precision fma (v_fma_mixlo/hi_f16), so
+        // the exact product is rounded once to nearest even; BF16 rounds the FP32
+        // product to nearest even on its bits.
         const float inv = m > 0.f ? 1.0f / m : 0.f;
         st_out<NT>(row_elem<float>(norm, 0, 0, cb), m);
 #pragma unroll
@@ -329,7 +373,7 @@ WL_HD void store_spinor(void *base, float *norm, int stride, int cb, const typen
 // One link as a 3x3 complex matrix.  base points at chunk 0 of the (parity, mu) block.
 // Link element load: non-temporal (NT) when each link is used once per launch,
 // plain when other right-hand sides of the launch re-read it from L2.
-template <bool NT, class CH> WL_HD CH ld_link(const CH *p)
+template <bool NT, class CH> WL_HD CH ld_link(const WL_G CH *p)
 {
     if constexpr (NT)
         return ld_stream(p);
@@ -413,8 +457,7 @@ WL_HD void store_link(void *base, int stride, int cb, const double u[18] /* row-
             b[(size_t)c * stride + cb] = float4{(float)u[4 * c], (float)u[4 * c + 1], (float)u[4 * c + 2], (float)u[4 * c + 3]};
     } else {
         for (int c = 0; c < 3; ++c)
-            b[(size_t)c * stride + cb] = uint2{pack2<P>((float)u[4 * c], (float)u[4 * c + 1]),
-                                               pack2<P>((float)u[4 * c + 2], (float)u[4 * c + 3])};
+            b[(size_t)c * stride + cb] = uint2{pack2_d<P>(u[4 * c], u[4 * c + 1]), pack2_d<P>(u[4 * c + 2], u[4 * c + 3])};
     }
 }
 
@@ -432,7 +475,22 @@ struct SysDesc {
     const void *gauge;   // packed links of the precision used by the launch
     const void *clov;    // packed clover term A (null: Wilson system), [parity][chunk][stride]
     const void *clovinv; // packed A^{-1}
+    double inv_lxh, inv_l1, inv_l2;  // 1/Lxh, 1/L[1], 1/L[2] for the coordinate divisions (set_divisors)
 };
+
+// the reciprocals cb_coords divides by (host side, once per geometry)
+inline void set_divisors(SysDesc &d)
+{
+    d.inv_lxh = 1.0 / d.Lxh;
+    d.inv_l1 = 1.0 / d.L[1];
+    d.inv_l2 = 1.0 / d.L[2];
+}
+
+// floor(n / d) for 0 <= n < 2^26 and 1 <= d <= 2^19, given inv = 1/d rounded to
+// FP64: n * inv is within 2^-26 of n/d, so adding 2^-20 lifts an exact quotient
+// clear of the truncation and stays below the next integer, which is at least
+// 1/d >= 2^-19 away (three FP64 instructions instead of an integer division)
+WL_HD int idiv(int n, double inv) { return (int)fma((double)n, inv, 0x1p-20); }
 
 // ------------------------------------------------------------------ clover term
 //
@@ -542,12 +600,12 @@ struct Site {
 WL_HD Site cb_coords(const SysDesc &d, int cb, int parity)
 {
     Site s;
-    int xh = cb % d.Lxh;
-    int r = cb / d.Lxh;
-    s.y = r % d.L[1];
-    r /= d.L[1];
-    s.z = r % d.L[2];
-    s.t = r / d.L[2];
+    const int r0 = idiv(cb, d.inv_lxh);  // cb = xh + Lxh (y + L1 (z + L2 t))
+    const int xh = cb - r0 * d.Lxh;
+    const int r1 = idiv(r0, d.inv_l1);
+    s.y = r0 - r1 * d.L[1];
+    s.t = idiv(r1, d.inv_l2);
+    s.z = r1 - s.t * d.L[2];
     s.x = 2 * xh + ((s.y + s.z + s.t + parity) & 1);
     return s;
 }
@@ -764,26 +822,33 @@ struct HopSite {
     float scale = 1.0f;   // FP16/BF16: factor folded into the accumulation (unused otherwise)
 };
 
-// Neighbour of site s in direction +-mu: its checkerboard index, and whether
-// the hop wraps the antiperiodic time boundary.
+// Neighbour of site s (checkerboard index cb) in direction +-mu: its
+// checkerboard index, and whether the hop wraps the antiperiodic time boundary.
+// In y, z and t the index moves by the direction's stride (Lxh, Lxh L1,
+// Lxh L1 L2), wrapping at the lattice edge; in x the neighbour of x = 2 xh + o
+// has half-index xh + o forwards and xh - (1 - o) backwards, wrapping in xh.
 template <int MU, int DIR>
-WL_HD int neighbour(const SysDesc &d, const Site &s, bool &flip)
+WL_HD int neighbour(const SysDesc &d, const Site &s, int cb, bool &flip)
 {
-    int nx = s.x, ny = s.y, nz = s.z, nt = s.t;
     flip = false;
-    if constexpr (MU == 0) nx = DIR > 0 ? (s.x + 1 == d.L[0] ? 0 : s.x + 1) : (s.x == 0 ? d.L[0] - 1 : s.x - 1);
-    if constexpr (MU == 1) ny = DIR > 0 ? (s.y + 1 == d.L[1] ? 0 : s.y + 1) : (s.y == 0 ? d.L[1] - 1 : s.y - 1);
-    if constexpr (MU == 2) nz = DIR > 0 ? (s.z + 1 == d.L[2] ? 0 : s.z + 1) : (s.z == 0 ? d.L[2] - 1 : s.z - 1);
-    if constexpr (MU == 3) {
-        if (DIR > 0) {
-            flip = (s.t + 1 == d.L[3]) && d.tap;
-            nt = s.t + 1 == d.L[3] ? 0 : s.t + 1;
+    if constexpr (MU == 0) {
+        const int o = s.x & 1, xh = s.x >> 1;
+        if constexpr (DIR > 0) return o ? (xh + 1 == d.Lxh ? cb - xh : cb + 1) : cb;
+        return o ? cb : (xh == 0 ? cb + d.Lxh - 1 : cb - 1);
+    } else {
+        const int c = MU == 1 ? s.y : MU == 2 ? s.z : s.t;
+        const int st = MU == 1 ? d.Lxh : MU == 2 ? d.Lxh * d.L[1] : d.Lxh * d.L[1] * d.L[2];
+        const int span = (d.L[MU] - 1) * st;  // from the last slice back to the first
+        if constexpr (DIR > 0) {
+            const bool w = c + 1 == d.L[MU];
+            if constexpr (MU == 3) flip = w && d.tap;
+            return w ? cb - span : cb + st;
         } else {
-            flip = (s.t == 0) && d.tap;
-            nt = s.t == 0 ? d.L[3] - 1 : s.t - 1;
+            const bool w = c == 0;
+            if constexpr (MU == 3) flip = w && d.tap;
+            return w ? cb + span : cb - st;
         }
     }
-    return (nx >> 1) + d.Lxh * (ny + d.L[1] * (nz + d.L[2] * nt));
 }
 
 // The spin projection of one neighbour spinor, and the factor its contribution
@@ -843,7 +908,7 @@ template <int SP, int GP, int R, int MU, int DIR, bool DAG, bool NT, class T>
 WL_HD void hop_dir(const SysDesc &d, const HopSite &a, int parity, const Site &s, int cb, T acc[24])
 {
     bool flip;
-    const int ncb = neighbour<MU, DIR>(d, s, flip);
+    const int ncb = neighbour<MU, DIR>(d, s, cb, flip);
     // forward hop carries 1 - gamma (sg = -1), backward 1 + gamma; adjoint swaps
     constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
     cpx<T> h0[3], h1[3];
@@ -860,7 +925,7 @@ WL_HD void hop_dir2(const SysDesc &d, const HopSite &a0, const HopSite &a1, int 
                     T acc0[24], T acc1[24])
 {
     bool flip;
-    const int ncb = neighbour<MU, DIR>(d, s, flip);
+    const int ncb = neighbour<MU, DIR>(d, s, cb, flip);
     constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
     cpx<T> u[3][3];
     hop_link<GP, R, MU, DIR, NT>(a0, parity, cb, ncb, u);

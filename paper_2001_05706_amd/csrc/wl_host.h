@@ -44,7 +44,16 @@ int nchunks(int prec);
 bool prec_recon_ok(int prec, int recon);
 int link_bytes(int prec, int recon);
 constexpr int kStrideAlign = 64;
-inline int padded(int vh) { return (vh + kStrideAlign - 1) / kStrideAlign * kStrideAlign; }
+// Chunk-row stride of a vector: Vh rounded up to a whole number of waves, made
+// an odd multiple of 64 sites.  Rows of a field (and the vectors of a set) then
+// start an odd multiple of 1 KiB apart instead of a large power of two apart,
+// so the rows a wave streams at once do not all fall into the same cache sets.
+inline int padded(int vh)
+{
+    int n = (vh + kStrideAlign - 1) / kStrideAlign;
+    if ((n & 1) == 0) ++n;
+    return n * kStrideAlign;
+}
 
 }  // namespace wl
 

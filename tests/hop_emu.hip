@@ -23,6 +23,7 @@ static void emu(const int32_t *L, int tap, const double *U, const double *in, do
     d.stride = (d.Vh + 63) / 64 * 64 + 64;  // padding differs from the library on purpose
     d.gstride = d.stride + 64;
     d.tap = tap;
+    set_divisors(d);
     constexpr int NCH = LinkFmt<P, R>::nchunk;
     using LCH = typename LinkFmt<P, R>::chunk;
     std::vector<LCH> links((size_t)8 * NCH * d.gstride);
@@ -84,4 +85,26 @@ extern "C" int emu_hop(int prec, int recon, int dag, const int32_t *L, int tap, 
 extern "C" void emu_xcd_remap(int nb, int32_t *out)
 {
     for (int h = 0; h < nb; ++h) out[h] = xcd_remap(h, nb);
+}
+
+// Checks idiv (the floating-point quotient of the coordinate code) against the
+// integer quotient for every divisor 1..dmax, at the multiples k d - 1, k d,
+// k d + 1 of the first and last 300 quotients below 2^26 and of 200 more spread
+// between them.  Returns the number of disagreements.
+extern "C" long emu_idiv_check(int dmax)
+{
+    long bad = 0;
+    const int64_t nmax = (int64_t)1 << 26;
+    for (int d = 1; d <= dmax; ++d) {
+        const double inv = 1.0 / d;
+        const int64_t kmax = (nmax - 1) / d;
+        auto check = [&](int64_t k) {
+            for (int64_t n = k * d - 1; n <= k * d + 1; ++n)
+                if (n >= 0 && n < nmax && idiv((int)n, inv) != (int)(n / d)) ++bad;
+        };
+        for (int64_t k = 0; k < 300 && k <= kmax; ++k) check(k);
+        for (int64_t k = kmax > 300 ? kmax - 300 : 0; k <= kmax + 1; ++k) check(k);
+        for (int64_t j = 1; j <= 200; ++j) check(kmax * j / 201);
+    }
+    return bad;
 }

@@ -255,3 +255,25 @@ def test_graph_replay_matches_eager(method, monkeypatch):
     assert ig == ie, (ig, ie)
     assert all(c for _, _, c in ig)
     assert np.array_equal(xg, xe)
+
+
+@pytest.mark.parametrize("sloppy", ["bf16", "f16"])
+def test_stagnation_raises_the_sloppy_precision(sloppy):
+    """With delta = 0.9 a reliable update follows every 10% fall of the sloppy
+    residual, so the FP64 residual cannot halve between two updates: the
+    stagnation rule restarts the search direction, and a second stall in a row
+    raises the sloppy storage (FP16/BF16 -> FP32 -> FP64), after folding the
+    sloppy solution into the FP64 accumulator.  The solve must still reach the
+    tolerance, confirmed by the oracle's operator, and agree with the oracle's
+    solution."""
+    w = need_gpu()
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2002)
+    st, info, x = solve(w, L, U, eta, 0.1245, 1e-10, sloppy, 12, delta=0.9, maxiter=5000)
+    assert info[0]["precision_escalations"] >= 1, info
+    assert info[0]["converged"] == 1, info
+    tr = true_resid(L, U, eta, x, 0.1245)
+    assert tr[0] <= 1e-10, tr
+    ref, _, _, _ = oracle.cg_eo(L, U, eta, 0.1245, 1e-12)
+    assert rel(x, ref) <= 2 * 20 * 1e-10

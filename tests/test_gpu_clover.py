@@ -5,7 +5,8 @@ import pytest
 
 import lattice_inputs as li
 import oracle
-from tests.gpu_util import from_dev, need_gpu, rel, to_dev
+from tests.gpu_util import (from_dev, half_storage_excess, need_gpu, quantize_links, quantize_spinor, rel,
+                            to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -38,21 +39,53 @@ def test_clover_dslash_matches_oracle(links, prec, recon, gate, dagger):
     g.close()
 
 
-@pytest.mark.parametrize("prec,gate", [("f16", 5e-3), ("bf16", 3e-2)])
+def clover_storage_model(A):
+    """The clover term as FP16/BF16 launches read it: two Hermitian 6x6 blocks
+    per site (spins 0-1 and 2-3, all colours), the 6 real diagonal entries and
+    the 15 complex entries above the diagonal each rounded once from FP64 to
+    the nearest FP16 value, the lower triangle their conjugates, nothing outside
+    the blocks."""
+    Aq = np.zeros_like(A)
+    for b in range(2):
+        blk = A[:, 6 * b:6 * b + 6, 6 * b:6 * b + 6]
+        re = blk.real.astype(np.float16).astype(np.float64)
+        im = blk.imag.astype(np.float16).astype(np.float64)
+        q = re + 1j * im
+        iu = np.triu_indices(6, 1)
+        full = np.zeros_like(q)
+        full[:, iu[0], iu[1]] = q[:, iu[0], iu[1]]
+        full[:, iu[1], iu[0]] = np.conj(q[:, iu[0], iu[1]])
+        d = np.arange(6)
+        full[:, d, d] = re[:, d, d]
+        Aq[:, 6 * b:6 * b + 6, 6 * b:6 * b + 6] = full
+    return Aq
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
 @pytest.mark.parametrize("dagger", [0, 1])
-def test_clover_dslash_half_precision(links, prec, gate, dagger):
-    """FP16/BF16 storage reads the FP16 copy of the clover term: the error
-    against the FP64 oracle stays at the storage rounding of spinors, links and
-    clover entries (2^-11 relative for FP16, 2^-8 for BF16)."""
+def test_clover_dslash_half_precision(links, prec, dagger):
+    """FP16/BF16 storage reads the FP16 copy of the clover term.  Compared with
+    the oracle's operator on the storage-rounded inputs (spinors with their site
+    norm, links rebuilt from two rounded rows, the clover term's packed entries
+    rounded to FP16): D psi = A psi - kappa H psi, with the oracle's A and H.
+    What remains is the output's rounding to storage, at most half a unit of a
+    value in [0.5, 1] times the site maximum (2^-12 FP16, 2^-9 BF16), plus the
+    FP32 arithmetic: per site, on the 24 reals, 1.01 x that + 1e-5 of the
+    field's mean site maximum."""
     w = need_gpu()
     psi = li.gaussian_spinor(L, 2305, nrhs=2)
-    ref = oracle.wilson_clover(L, links, psi, KAPPA, CSW, dagger=bool(dagger))
+    V = li.volume(L)
+    pq = quantize_spinor(psi, prec)
+    Uq = quantize_links(links, prec, 12)
+    Aq = clover_storage_model(oracle.clover(L, links, KAPPA, CSW))
+    Apsi = np.einsum("vij,rvj->rvi", Aq, pq.reshape(2, V, 12)).reshape(psi.shape)
+    ref = Apsi - KAPPA * oracle.hop(L, Uq, pq, dagger=bool(dagger))
     g = w.Gauge(L, to_dev(links))
     out = to_dev(np.zeros_like(psi))
     w.wilson_clover_dslash(g, to_dev(psi), out, 2, KAPPA, CSW, dagger, prec, 12)
     got = from_dev(out, psi.shape)
-    for r in range(2):
-        assert rel(got[r], ref[r]) <= gate, (r, rel(got[r], ref[r]))
+    e = half_storage_excess(got, ref, prec)
+    assert e <= 1e-5, (prec, dagger, e)
     g.close()
 
 

@@ -1,7 +1,8 @@
 """Full-size GPU cases of the benchmark configurations, checked through the
-FP64 oracle where it can afford it (whole-lattice true residuals, one sampled
-right-hand side of the sign function) and through properties that hold at any
-size otherwise.
+FP64 oracle where it can afford it (whole-lattice true residuals; the sign
+function of every right-hand side at sampled sites and projections the oracle
+computed once, and one right-hand side in full) and through properties that
+hold at any size otherwise.
 
   mixed precision   32^3 x 64, eps 0.3 links, kappa 0.1248, FP16 and BF16
                     sloppy with recon-12 links, true residual 1e-10
@@ -9,6 +10,9 @@ size otherwise.
   uneven batch      4 x {8^4, 12^4, 16^3 x 32, 24^3 x 48} in one batched solve
   sign function     16^3 x 32, eps 0.2 links, rho 1.5, degree 200, 12 RHS, FP32
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -77,20 +81,44 @@ def test_uneven_batch_full_size():
 
 
 def test_sign_function_16c32_twelve_rhs():
-    """GPU FP32 on 12 RHS; the oracle recomputes one sampled RHS in full.
+    """GPU FP32 on the 12 RHS of the sign-function workload, every RHS checked
+    against the FP64 oracle: at 32 sampled sites each and by two projections
+    onto fixed random fields (values the oracle computed once for all 12 RHS,
+    stored by tests/golden/make_sign_samples.py), and one RHS in full.  A swap
+    of two RHS, or an error confined to one, fails the per-RHS checks.
 
     scale = 42.25 bounds lambda_max(H_W^2) for any SU(3) field:
     |H_W| <= |4 - rho| + |H|/2 <= 2.5 + 4 (|H| <= 8 for unitary links)."""
+    from tests.golden.make_sign_samples import sample_plan
+
     w = need_gpu()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sign_16c32_samples.json")))
     L = (16, 16, 16, 32)
+    rho, deg, lo, hi, scale = 1.5, 200, 0.003, 1.0, 42.25
+    assert tuple(gold["lattice"]) == L and (gold["rho"], gold["degree"], gold["lo"], gold["hi"], gold["scale"]) == \
+        (rho, deg, lo, hi, scale) and gold["links"] == {"eps": 0.2, "seed": 1005} and gold["source_seed"] == 2005
     U = li.near_identity_links(L, 0.2, 1005)
     psi = li.gaussian_spinor(L, 2005, nrhs=12)
-    rho, deg, lo, hi, scale = 1.5, 200, 0.003, 1.0, 42.25
+    V = li.volume(L)
     g = w.Gauge(L, to_dev(U))
     out = to_dev(np.zeros_like(psi))
     w.overlap_sign_cheb(g, to_dev(psi), out, 12, rho, deg, lo, hi, scale, "f32", 12)
     got = from_dev(out, psi.shape)
-    k = 7  # sampled right-hand side
+    sites, wproj = sample_plan()
+    assert np.array_equal(sites, np.asarray(gold["sites"]))
+    for k in range(12):
+        nrm = gold["norm"][k]
+        rms = nrm / np.sqrt(12 * V)  # root mean square of one complex component
+        want = np.asarray(gold["values"][k]).view(np.complex128).reshape(-1, 12)
+        have = got[k][sites[k]].reshape(-1, 12)
+        e_site = float(np.abs(have - want).max() / rms)
+        assert e_site <= 1e-4, (k, e_site)
+        for j in range(gold["nproj"]):
+            pj = complex(*gold["proj"][k][j])
+            e_proj = abs(np.vdot(wproj[j], got[k]) - pj) / nrm
+            assert e_proj <= 1e-4, (k, j, e_proj)
+        assert abs(np.linalg.norm(got[k]) / nrm - 1) <= 1e-5
+    k = 7  # one right-hand side in full
     ref = oracle.sign_cheb(L, U, psi[k], rho, deg, lo, hi, scale)
     assert rel(got[k], ref) <= 1e-5
     # eps^2 = 1 and norm preservation on every RHS (FP32 arithmetic)

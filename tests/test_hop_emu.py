@@ -27,6 +27,8 @@ def emu(tmp_path_factory):
     lib.emu_hop.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 3 + [ctypes.c_int]
     lib.emu_hop.restype = ctypes.c_int
     lib.emu_xcd_remap.argtypes = [ctypes.c_int, ctypes.c_void_p]
+    lib.emu_idiv_check.argtypes = [ctypes.c_int]
+    lib.emu_idiv_check.restype = ctypes.c_long
     return lib
 
 
@@ -60,3 +62,11 @@ def test_xcd_remap_is_a_bijection(emu):
         out = np.zeros(nb, dtype=np.int32)
         emu.emu_xcd_remap(nb, out.ctypes.data)
         assert np.array_equal(np.sort(out), np.arange(nb))
+
+
+def test_coordinate_division_is_exact(emu):
+    """The site-coordinate code divides by the lattice extents with one FP64
+    multiply-add by the reciprocal (idiv); it must equal the integer quotient
+    for every extent the library accepts (up to 65536) and every checkerboard
+    index below 2^26, checked at and around exact multiples."""
+    assert emu.emu_idiv_check(65536) == 0
