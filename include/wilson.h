@@ -115,6 +115,24 @@ void wl_gauge_destroy(wl_gauge U);
 wl_status wilson_dslash(wl_gauge U, const double *in, double *out, int32_t nrhs, double kappa,
                         int32_t parity, int32_t dagger, wl_prec prec, int32_t recon, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * operation as wilson_dslash (same arguments, kernels and results), with every
+ * buffer beyond `in` and `out` -- descriptor tables, the links packed from the
+ * handle's canonical copy, the packed input and output fields -- kept in one
+ * library-owned device array of WL_NOALLOC_SCRATCH_BYTES per GPU, which the
+ * library holds from its first call on that GPU until the process ends.  The
+ * call issues no hipMalloc, hipFree or memset.  A lattice and nrhs whose packed
+ * fields and links do not fit that array return WL_ERR_ARG before any device
+ * work (about: links 8 V/2 x (link bytes) + 2 or 4 fields of nrhs V/2 x (site
+ * bytes); 16^4 in FP64 recon-18 with one RHS fits, 24^4 in FP16 fits).  The
+ * current device must be the handle's.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (several streams or host threads) race,
+ * so the caller orders them.  Asynchronous on `stream`. */
+#define WL_NOALLOC_SCRATCH_BYTES (128u << 20)
+wl_status wilson_dslash_noalloc(wl_gauge U, const double *in, double *out, int32_t nrhs, double kappa,
+                                int32_t parity, int32_t dagger, wl_prec prec, int32_t recon, void *stream);
+
 /* ---------------------------------------------------------------- solvers */
 
 /* Solve D psi = eta (kappa normalisation) for nrhs right-hand sides by

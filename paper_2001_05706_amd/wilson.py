@@ -57,6 +57,7 @@ SIGNATURES = [
     ("wl_gauge_create", _i32, [ctypes.POINTER(WlGeom), _P, _P, ctypes.POINTER(_P)]),
     ("wl_gauge_destroy", None, [_P]),
     ("wilson_dslash", _i32, [_P, _P, _P, _i32, _d, _i32, _i32, _i32, _i32, _P]),
+    ("wilson_dslash_noalloc", _i32, [_P, _P, _P, _i32, _d, _i32, _i32, _i32, _i32, _P]),
     ("wilson_cg", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _i32, _i32, _d, ctypes.POINTER(WlSolveInfo), _P]),
     ("wilson_bicgstab", _i32, [_P, _P, _P, _i32, _d, _d, _i32, _i32, _i32, _d, ctypes.POINTER(WlSolveInfo), _P]),
     ("wilson_cg_multi", _i32, [_i32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
@@ -178,6 +179,11 @@ def wl_gauge_destroy(g: Gauge):
 def wilson_dslash(U: Gauge, inp, out, nrhs, kappa, parity, dagger=0, prec="f32", recon=12, stream=None):
     return _check(lib().wilson_dslash(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(kappa),
                                       int(parity), int(dagger), _prec(prec), int(recon), _stream(stream)))
+
+
+def wilson_dslash_noalloc(U: Gauge, inp, out, nrhs, kappa, parity, dagger=0, prec="f32", recon=12, stream=None):
+    return _check(lib().wilson_dslash_noalloc(U.handle, _ptr(inp, "in"), _ptr(out, "out"), int(nrhs), float(kappa),
+                                              int(parity), int(dagger), _prec(prec), int(recon), _stream(stream)))
 
 
 def wilson_cg(U: Gauge, eta, x, nrhs, kappa, tol, maxiter, sloppy="f32", recon=12, delta=0.1, stream=None,
