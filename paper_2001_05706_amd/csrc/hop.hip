@@ -44,15 +44,32 @@ template <int SP, int VAR> struct HopVar {
     static constexpr bool nt = VAR < 3;
     static constexpr bool rhs_waves = VAR == 6;
     static constexpr bool rhs_pairs = VAR == 7;
+    // largest block: 1024 threads (16 waves on one CU, 4 per SIMD) where the
+    // occupancy target already allows 4 waves per SIMD; 512 otherwise
+    static constexpr int max_block = waves >= 4 && VAR < 6 ? 1024 : 512;
 };
 constexpr int kHopVariants = 8;
+
+// The fields of the output parity a block computes: the launch's first slot,
+// or for the second half of a twin launch the second one.  X and Xn point into
+// the kernel's argument block, so that an index that varies at run time still
+// reads them with scalar loads.
+struct HopIO {
+    int parity;
+    const void *in;
+    const float *in_norm;
+    void *out;
+    float *out_norm;
+    const void *const *X;
+    const float *const *Xn;
+};
 
 // Everything after the hopping sum at one output site of one vector: the
 // linear-combination epilogue, the store, and the site's reduction values.
 // acc holds H psi (FP16/BF16: already multiplied by the system's c).
 template <int SP, bool CLOV>
-__device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd, const SysDesc &sd, int cb,
-                                             typename SpinorFmt<SP>::real acc[24], double rv[3])
+__device__ __forceinline__ void hop_epilogue(const HopArgs &a, const HopIO &f, const VecDesc &vd, const SysDesc &sd,
+                                             int cb, typename SpinorFmt<SP>::real acc[24], double rv[3])
 {
     using T = typename SpinorFmt<SP>::real;
     using CH = typename SpinorFmt<SP>::chunk;
@@ -73,19 +90,19 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd
     T o[24];
     if (a.epi.nx >= 1) {
         // operand values before their site norm; the norm joins the coefficient
-        T x[24], n0;
+        T x[24], n0 = 1;
         bool raw = true;
         if constexpr (CLOV) {
             if (clov && (a.epi.clov & EPI_CLOV_X0)) {
-                load_spinor<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
+                load_spinor<SP>((const CH *)f.X[0] + voff, f.Xn[0] ? f.Xn[0] + vd.site_off : nullptr,
                                 sd.stride, cb, x);
-                clover_apply<CP>(clover_parity<CP>(sd.clov, a.parity, sd.stride), sd.stride, cb, x);
+                clover_apply<CP>(clover_parity<CP>(sd.clov, f.parity, sd.stride), sd.stride, cb, x);
                 n0 = 1;
                 raw = false;
             }
         }
         if (raw)
-            load_spinor_raw<SP>((const CH *)a.epi.X[0] + voff, a.epi.Xn[0] ? a.epi.Xn[0] + vd.site_off : nullptr,
+            load_spinor_raw<SP>((const CH *)f.X[0] + voff, f.Xn[0] ? f.Xn[0] + vd.site_off : nullptr,
                                 sd.stride, cb, x, &n0);
         const T s0 = (T)cf[0] * n0;
 #pragma unroll
@@ -100,17 +117,17 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd
     }
     if constexpr (CLOV) {
         if (clov && (a.epi.clov & EPI_CLOV_INV))
-            clover_apply<CP>(clover_parity<CP>(sd.clovinv, a.parity, sd.stride), sd.stride, cb, o);
+            clover_apply<CP>(clover_parity<CP>(sd.clovinv, f.parity, sd.stride), sd.stride, cb, o);
     }
     for (int j = 1; j < a.epi.nx; ++j) {
         T x[24], nj;
-        load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+        load_spinor_raw<SP>((const CH *)f.X[j] + voff, f.Xn[j] ? f.Xn[j] + vd.site_off : nullptr,
                             sd.stride, cb, x, &nj);
         const T sj = (T)cf[j] * nj;
 #pragma unroll
         for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], sj, o[k]);
     }
-    store_spinor<SP, true>((CH *)a.out + voff, a.out_norm ? a.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
+    store_spinor<SP, true>((CH *)f.out + voff, f.out_norm ? f.out_norm + vd.site_off : nullptr, sd.stride, cb, o);
     if (a.red.kind != RED_NONE) {
         if (a.red.mode == RM_NORM) {
             rv[0] = site_norm2(o);
@@ -119,7 +136,7 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd
             // products are linear in x: its site norm scales the site sums.
             const int j = a.red.mode == RM_DOT_X1 ? 1 : 0;
             T x[24], nx;
-            load_spinor_raw<SP>((const CH *)a.epi.X[j] + voff, a.epi.Xn[j] ? a.epi.Xn[j] + vd.site_off : nullptr,
+            load_spinor_raw<SP>((const CH *)f.X[j] + voff, f.Xn[j] ? f.Xn[j] + vd.site_off : nullptr,
                                 sd.stride, cb, x, &nx);
             if (a.red.mode == RM_DOT_X1) {
                 site_cdot(x, o, rv[0], rv[1]);
@@ -134,13 +151,13 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const VecDesc &vd
 }
 
 template <int SP>
-__device__ __forceinline__ HopSite hop_input(const HopArgs &a, const VecDesc &vd, const SysDesc &sd)
+__device__ __forceinline__ HopSite hop_input(const HopArgs &a, const HopIO &f, const VecDesc &vd, const SysDesc &sd)
 {
     using CH = typename SpinorFmt<SP>::chunk;
     constexpr bool HALF = SP == P_F16 || SP == P_BF16;
     HopSite hs;
-    hs.in = (const CH *)a.in + (size_t)vd.site_off * SpinorFmt<SP>::nchunk;
-    hs.in_norm = a.in_norm ? a.in_norm + vd.site_off : nullptr;
+    hs.in = (const CH *)f.in + (size_t)vd.site_off * SpinorFmt<SP>::nchunk;
+    hs.in_norm = f.in_norm ? f.in_norm + vd.site_off : nullptr;
     hs.stride = sd.stride;
     hs.gauge = sd.gauge;
     hs.gstride = sd.gstride;
@@ -149,14 +166,21 @@ __device__ __forceinline__ HopSite hop_input(const HopArgs &a, const VecDesc &vd
 }
 
 template <int SP, int GP, int R, bool DAG, int VAR, bool CLOV>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves))) void k_hop(HopArgs a)
+__global__ __launch_bounds__((HopVar<SP, VAR>::max_block)) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves)))
+void k_hop(HopArgs a)
 {
     using T = typename SpinorFmt<SP>::real;
 
     constexpr bool RW = HopVar<SP, VAR>::rhs_waves;
     constexpr bool PAIR = HopVar<SP, VAR>::rhs_pairs;
     const int lb = xcd_remap(blockIdx.x, a.nblocks);
-    const BlkMap bm = a.map[lb];
+    // a twin launch's second half computes the other output parity from the
+    // second field slot (the selection is uniform over the block)
+    const int half = a.nblocks >> 1;
+    const bool second = a.twin && lb >= half;
+    const HopIO f = second ? HopIO{1 - a.parity, a.in_b, a.in_norm_b, a.out_b, a.out_norm_b, a.X_b, a.Xn_b}
+                           : HopIO{a.parity, a.in, a.in_norm, a.out, a.out_norm, a.epi.X, a.epi.Xn};
+    const BlkMap bm = a.map[second ? lb - half : lb];
     int v = bm.v, cb;
     bool valid = true;
     if constexpr (RW) {
@@ -192,11 +216,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
         const VecDesc vd1 = a.vec[has1 ? v1 : bm.v];
         double rv0[3] = {0.0, 0.0, 0.0}, rv1[3] = {0.0, 0.0, 0.0};
         if (cb < sd.Vh) {
-            const HopSite hs0 = hop_input<SP>(a, vd, sd), hs1 = hop_input<SP>(a, vd1, sd);
+            const HopSite hs0 = hop_input<SP>(a, f, vd, sd), hs1 = hop_input<SP>(a, f, vd1, sd);
             T acc0[24], acc1[24];
-            hop_site2<SP, GP, R, DAG, HopVar<SP, VAR>::nt>(sd, hs0, hs1, a.parity, cb, acc0, acc1);
-            if (live0) hop_epilogue<SP, CLOV>(a, vd, sd, cb, acc0, rv0);
-            if (live1) hop_epilogue<SP, CLOV>(a, vd1, sd, cb, acc1, rv1);
+            hop_site2<SP, GP, R, DAG, HopVar<SP, VAR>::nt>(sd, hs0, hs1, f.parity, cb, acc0, acc1);
+            if (live0) hop_epilogue<SP, CLOV>(a, f, vd, sd, cb, acc0, rv0);
+            if (live1) hop_epilogue<SP, CLOV>(a, f, vd1, sd, cb, acc1, rv1);
         }
         // live0 and live1 are uniform over the block
         if (a.red.kind != RED_NONE && live0) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv0);
@@ -204,10 +228,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, 
     } else {
         double rv[3] = {0.0, 0.0, 0.0};
         if (valid && cb < sd.Vh) {
-            const HopSite hs = hop_input<SP>(a, vd, sd);
+            const HopSite hs = hop_input<SP>(a, f, vd, sd);
             T acc[24];
-            hop_site<SP, GP, R, DAG, HopVar<SP, VAR>::fence, HopVar<SP, VAR>::nt>(sd, hs, a.parity, cb, acc);
-            hop_epilogue<SP, CLOV>(a, vd, sd, cb, acc, rv);
+            hop_site<SP, GP, R, DAG, HopVar<SP, VAR>::fence, HopVar<SP, VAR>::nt>(sd, hs, f.parity, cb, acc);
+            hop_epilogue<SP, CLOV>(a, f, vd, sd, cb, acc, rv);
         }
         if constexpr (RW) {
             if (a.red.kind != RED_NONE && valid) wave_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);

@@ -134,19 +134,31 @@ static std::map<std::string, int> g_tuned;
 int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream_t s,
                 const std::function<hipError_t(int)> &run)
 {
-    // WL_TUNE_FORCE=<config> pins every hop launch to one candidate (tests of each variant)
+    // WL_TUNE_FORCE=<variant>:<block>[:<column height>] pins every hop launch
+    // to one candidate (tests of each variant; column height 4 by default)
     const char *force = getenv("WL_TUNE_FORCE");
     if (force && key.compare(0, 4, "hop/") == 0) {
-        const int c = atoi(force);
-        for (int x : cands)
-            if (x == c) return c;
+        int v = -1, b = -1, col = 4;
+        if (sscanf(force, "%d:%d:%d", &v, &b, &col) >= 2) {
+            const int c = cfg_make(v, b, col);
+            for (int x : cands)
+                if (x == c) return c;
+        }
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) return it->second;
     }
-    const int fallback = 256;
+    // untuned (tuning switched off, or first met inside a graph capture, where
+    // nothing may be timed): 256-thread blocks in columns of 4 z-planes
+    if (cands.empty()) return cfg_make(0, 256, 4);
+    int fallback = cands[0];
+    for (int c : cands)
+        if (cfg_block(c) == 256 && cfg_col(c) == 4) {
+            fallback = c;
+            break;
+        }
     const char *env = getenv("WL_TUNE");
     if ((env && env[0] == '0') || capturing(s)) return fallback;
     hipEvent_t e0, e1;
@@ -421,9 +433,11 @@ wl_status ExecSet::sys_table(int prec, int recon, hipStream_t s, const SysDesc *
     return WL_OK;
 }
 
-wl_status ExecSet::layout(int B, const Layout **out)
+wl_status ExecSet::layout(int B, const Layout **out, int col)
 {
-    auto it = layouts.find(B);
+    if (col < 1) return set_error(WL_ERR_ARG, "column height %d must be >= 1", col);
+    const auto lkey = std::make_pair(B, col);
+    auto it = layouts.find(lkey);
     if (it != layouts.end()) {
         *out = &it->second;
         return WL_OK;
@@ -448,15 +462,16 @@ wl_status ExecSet::layout(int B, const Layout **out)
         // logical order (system, site block, rhs): right-hand sides sharing links
         // are adjacent.  Site blocks go in time groups of ceil(Lt / 8) slices
         // (one XCD's contiguous share of the launch), and inside a group in
-        // columns of 4 z-planes swept along t, so a neighbour in t is 4 planes
-        // away in launch order rather than a whole slice: the spinors a wave's
-        // neighbours need are still in the XCD's L2 when they are read.
+        // columns of `col` z-planes swept along t, so a neighbour in t is `col`
+        // planes away in launch order rather than a whole slice: the spinors a
+        // wave's neighbours need are still in the XCD's L2 when they are read.
+        // (The tuner chooses the column height with the launch variant.)
         const SysDesc &g = systems[i].g->geom;
         const int plane = g.Lxh * g.L[1], slice = plane * g.L[2], tg = (g.L[3] + 7) / 8;
         std::vector<std::array<int, 5>> key(nb);
         for (int b = 0; b < nb; ++b) {
             const int cb0 = b * sites, t = cb0 / slice, z = (cb0 % slice) / plane;
-            key[b] = {t / tg, z / 4, t, z, b};
+            key[b] = {t / tg, z / col, t, z, b};
         }
         std::sort(key.begin(), key.end());
         for (int k = 0; k < nb; ++k)
@@ -470,8 +485,8 @@ wl_status ExecSet::layout(int B, const Layout **out)
     WL_ALLOC(L.d_map, sizeof(BlkMap) * map.size());
     WL_HIP(hipMemcpy(L.d_vec, hv.data(), sizeof(VecDesc) * hv.size(), hipMemcpyHostToDevice));
     WL_HIP(hipMemcpy(L.d_map, map.data(), sizeof(BlkMap) * map.size(), hipMemcpyHostToDevice));
-    layouts[B] = L;
-    *out = &layouts[B];
+    layouts[lkey] = L;
+    *out = &layouts[lkey];
     return WL_OK;
 }
 
@@ -644,22 +659,36 @@ std::string hop_key(const ExecSet &S, int prec, int recon, bool dag)
            set_sig(S);
 }
 
-// (variant, block size) pairs encoded as variant * 1024 + block
+// Hop launch configurations (variant, block size, column height of the block
+// order) encoded as one integer.
+int cfg_make(int var, int block, int col) { return var | (block << 4) | (col << 16); }
+int cfg_var(int c) { return c & 15; }
+int cfg_block(int c) { return (c >> 4) & 4095; }
+int cfg_col(int c) { return c >> 16; }
+
+// Candidate configurations: every variant x block size x column height of 4 or
+// 16 z-planes (taller columns sweep longer runs of consecutive sites: FP64
+// 32^3 x 64 D-slash 291 -> 278 us, FP32 116 -> 114 us; at 24^3 x 48 the height
+// changes little)
 std::vector<int> hop_candidates(int prec)
 {
     const bool half = prec == P_F16 || prec == P_BF16;
     std::vector<int> c;
-    for (int v = 0; v < hop_variants(prec); ++v) {
-        if ((v == 4 || v == 5) && !half) continue;  // four directions in flight: half precision only
-        if (v == 6) {
-            for (int b : {256, 512}) c.push_back(v * 1024 + b);  // 4 or 8 right-hand sides per block
-            continue;
+    for (int col : {4, 16})
+        for (int v = 0; v < hop_variants(prec); ++v) {
+            if ((v == 4 || v == 5) && !half) continue;  // four directions in flight: half precision only
+            if (v == 6) {
+                for (int b : {256, 512}) c.push_back(cfg_make(v, b, col));  // 4 or 8 right-hand sides per block
+                continue;
+            }
+            // two FP64 accumulators fit only at 2 waves per SIMD, where variant 7 measured
+            // slower than 3 and 6 (12-RHS recon-12 D-slash: 700 us against 672 us)
+            if (v == 7 && prec == P_F64) continue;
+            for (int b : {64, 128, 256, 512}) c.push_back(cfg_make(v, b, col));
+            // 1024-thread blocks where the variant runs 4 or more waves per SIMD
+            // (FP32 and half-precision storage, variants 0-5; see HopVar::max_block)
+            if (v < 6 && prec != P_F64) c.push_back(cfg_make(v, 1024, col));
         }
-        // two FP64 accumulators fit only at 2 waves per SIMD, where variant 7 measured
-        // slower than 3 and 6 (12-RHS recon-12 D-slash: 700 us against 672 us)
-        if (v == 7 && prec == P_F64) continue;
-        for (int b : {64, 128, 256, 512}) c.push_back(v * 1024 + b);
-    }
     return c;
 }
 
@@ -668,8 +697,8 @@ std::vector<int> hop_candidates(int prec)
 // right-hand sides
 static wl_status hop_layout(ExecSet &S, int cfg, const Layout **L)
 {
-    const int var = cfg / 1024, B = cfg % 1024;
-    return S.layout(var == 6 ? -(B / 64) : var == 7 ? kPairLayout + B : B, L);
+    const int var = cfg_var(cfg), B = cfg_block(cfg);
+    return S.layout(var == 6 ? -(B / 64) : var == 7 ? kPairLayout + B : B, L, cfg_col(cfg));
 }
 
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
@@ -709,21 +738,22 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
                             (red.kind != RED_NONE ? "/r" : "");
     std::vector<int> cands = hop_candidates(prec);
     if (clov)  // the clover epilogue needs the registers of the two-direction variants (0 and 3)
-        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 == 1 || c / 1024 == 2; }),
+        cands.erase(std::remove_if(cands.begin(), cands.end(),
+                                   [](int c) { return cfg_var(c) == 1 || cfg_var(c) == 2; }),
                     cands.end());
     int max_nrhs = 0;
     for (auto &e : S.systems) max_nrhs = std::max(max_nrhs, e.nrhs);
     if (max_nrhs < 2)  // right-hand-side blocks and pairs need several right-hand sides
-        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return c / 1024 >= 6; }), cands.end());
+        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return cfg_var(c) >= 6; }), cands.end());
     if (cands.empty()) cands = hop_candidates(prec);
     const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;
         if (hop_layout(S, c, &L) != WL_OK) return hipErrorOutOfMemory;
         // with the launch's own reduction: the partial slots it writes are
         // rewritten by the launch that follows the tuning
-        return launch_hop(prec, recon, dag, clov, c / 1024, mk(L, red), c % 1024, s);
+        return launch_hop(prec, recon, dag, clov, cfg_var(c), mk(L, red), cfg_block(c), s);
     });
-    const int B = cfg % 1024, var = cfg / 1024;
+    const int B = cfg_block(cfg), var = cfg_var(cfg);
     const Layout *L = nullptr;
     WL_TRY(hop_layout(S, cfg, &L));
     const double bytes = hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e.nx, use_active) +
@@ -771,6 +801,66 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         WL_HIP(launch_hop(prec, recon, dag, clov, var, mk(L, red), B, s));
     }
     if (red.kind != RED_NONE) WL_HIP(launch_red_finalize(red, L->d_vec, use_active ? S.d_active : nullptr, S.nvec, s));
+    return WL_OK;
+}
+
+wl_status hop2(ExecSet &S, int prec, int recon, bool dag, const Field out[2], const Field in[2], const Epi e[2],
+               hipStream_t s, bool use_active)
+{
+    // one launch for both output parities: a single-vector set has only one
+    // wave per SIMD per parity on a small lattice, and the two halves of a
+    // whole-lattice operator are independent.  Otherwise (several vectors, a
+    // clover term, different epilogue shapes, kernel timing) two launches.
+    const bool clov = (e[0].clov != 0 || e[1].clov != 0) && S.has_clover;
+    if (S.nvec != 1 || clov || prof().on || e[0].nx != e[1].nx || e[0].g5 != e[1].g5 || e[0].coef != e[1].coef) {
+        for (int p = 0; p < 2; ++p) WL_TRY(hop(S, prec, recon, dag, p, out[p], in[1 - p], e[p], no_red(), s, use_active));
+        return WL_OK;
+    }
+    const SysDesc *sysd = nullptr;
+    WL_TRY(S.sys_table(prec, recon, s, &sysd));
+    auto mk = [&](const Layout *L) {
+        HopArgs a{};
+        a.sys = sysd;
+        a.vec = L->d_vec;
+        a.map = L->d_map;
+        a.active = use_active ? S.d_active : nullptr;
+        a.nblocks = 2 * L->nblocks;
+        a.parity = 0;
+        a.nvec = S.nvec;
+        a.in = in[1].p;
+        a.in_norm = in[1].n;
+        a.out = out[0].p;
+        a.out_norm = out[0].n;
+        a.epi.nx = e[0].nx;
+        a.epi.g5 = e[0].g5;
+        a.epi.coef = e[0].coef;
+        for (int j = 0; j < 4; ++j) {
+            a.epi.X[j] = e[0].X[j].p;
+            a.epi.Xn[j] = e[0].X[j].n;
+            a.X_b[j] = e[1].X[j].p;
+            a.Xn_b[j] = e[1].X[j].n;
+        }
+        a.red = no_red();
+        a.one = 1;
+        a.twin = 1;
+        a.in_b = in[0].p;
+        a.in_norm_b = in[0].n;
+        a.out_b = out[1].p;
+        a.out_norm_b = out[1].n;
+        return a;
+    };
+    const std::string key = hop_key(S, prec, recon, dag) + "/twin/x" + std::to_string(e[0].nx);
+    std::vector<int> cands = hop_candidates(prec);
+    cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return cfg_var(c) >= 6; }), cands.end());
+    const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
+        const Layout *L = nullptr;
+        if (hop_layout(S, c, &L) != WL_OK) return hipErrorOutOfMemory;
+        return launch_hop(prec, recon, dag, false, cfg_var(c), mk(L), cfg_block(c), s);
+    });
+    const Layout *L = nullptr;
+    WL_TRY(hop_layout(S, cfg, &L));
+    g_bytes_acc += 2 * (hop_bytes(S, prec, recon, use_active) + blas_bytes(S, prec, e[0].nx, use_active));
+    WL_HIP(launch_hop(prec, recon, dag, false, cfg_var(cfg), mk(L), cfg_block(cfg), s));
     return WL_OK;
 }
 
@@ -1167,7 +1257,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
         cfg = tuned_block(hop_key(*S, prec, recon, false) + "/x0", hop_candidates(prec), s,
                           [](int) { return hipSuccess; });
-        B = cfg % 1024;
+        B = cfg_block(cfg);
         if (st == WL_OK) st = hop_layout(*S, cfg, &L);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1190,7 +1280,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
             a.epi.coef = coef;
             a.red = no_red();
             a.one = S->nvec == 1;  // as the solvers launch it
-            return launch_hop(prec, recon, false, false, cfg / 1024, a, B, s);
+            return launch_hop(prec, recon, false, false, cfg_var(cfg), a, B, s);
         };
         for (int k = 0; k < nsets && st == WL_OK; ++k)
             if (launch(k) != hipSuccess) st = set_error(WL_ERR_HIP, "hop launch failed");

@@ -39,14 +39,15 @@ static std::vector<double> invsqrt_coeffs(int degree, double lo, double hi)
 wl_status apply_hw(ExecSet &S, int prec, int recon, const Field out[2], const Field in[2], const double *coef,
                           const RedSpec *red, hipStream_t s)
 {
+    Epi e[2];
     for (int p = 0; p < 2; ++p) {
-        Epi e;
-        e.coef = coef;
-        e.g5 = 1;
-        e.nx = 1;
-        e.X[0] = in[p];
-        WL_TRY(hop(S, prec, recon, false, p, out[p], in[1 - p], e, red ? red[p] : no_red(), s));
+        e[p].coef = coef;
+        e[p].g5 = 1;
+        e[p].nx = 1;
+        e[p].X[0] = in[p];
     }
+    if (!red) return hop2(S, prec, recon, false, out, in, e, s);
+    for (int p = 0; p < 2; ++p) WL_TRY(hop(S, prec, recon, false, p, out[p], in[1 - p], e[p], red[p], s));
     return WL_OK;
 }
 
@@ -136,18 +137,17 @@ wl_status sign_poly(ExecSet &S, int prec, int recon, const SignPlan &P, const Fi
     auto step = [&](const double *coef, const Field *dst) -> wl_status {
         // w = H_W b_{j+1};  dst = g5(a0 w + c hop w) + a1 b_{j+1} + a2 b_{j+2} + a3 v
         WL_TRY(apply_hw(S, prec, recon, w, b[i1], P.tab, nullptr, s));
+        Epi e[2];
         for (int p = 0; p < 2; ++p) {
-            Epi e;
-            e.coef = coef;
-            e.g5 = 1;
-            e.nx = 4;
-            e.X[0] = w[p];
-            e.X[1] = b[i1][p];
-            e.X[2] = b[i2][p];
-            e.X[3] = v[p];
-            WL_TRY(hop(S, prec, recon, false, p, dst[p], w[1 - p], e, no_red(), s));
+            e[p].coef = coef;
+            e[p].g5 = 1;
+            e[p].nx = 4;
+            e[p].X[0] = w[p];
+            e[p].X[1] = b[i1][p];
+            e[p].X[2] = b[i2][p];
+            e[p].X[3] = v[p];
         }
-        return WL_OK;
+        return hop2(S, prec, recon, false, dst, w, e, s);
     };
     for (int j = P.N - 1; j >= 1; --j) {
         WL_TRY(step(P.tab + 5 * j, b[i0]));

@@ -384,8 +384,6 @@ template <bool NT, class CH> WL_HD CH ld_link(const WL_G CH *p)
 template <int P, int R, class T, bool NT = true>
 WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
 {
-    using F = LinkFmt<P, R>;
-    const typename F::chunk *b = (const typename F::chunk *)base;
     if constexpr (P == P_F64) {
 #pragma unroll
         for (int k = 0; k < (R == 18 ? 9 : 6); ++k) {

@@ -131,7 +131,8 @@ public:
     wl_status sys_table(int prec, int recon, hipStream_t s, const SysDesc **out);
     // B > 0: blocks of B sites of one vector; B < 0: blocks of -B vectors on 64
     // sites; B >= kPairLayout: blocks of B - kPairLayout sites of two vectors
-    wl_status layout(int B, const Layout **out);
+    // col: z-planes per column of the block order (see the definition)
+    wl_status layout(int B, const Layout **out, int col = 4);
     int32_t *d_active = nullptr;
     std::vector<int32_t> h_active;
     // copy h_active to d_active, ordered on the stream (no host synchronisation);
@@ -165,7 +166,7 @@ public:
     std::map<std::string, std::pair<void *, size_t>> bufs;
 
     std::map<std::pair<int, int>, SysDesc *> d_sys;
-    std::map<int, Layout> layouts;
+    std::map<std::pair<int, int>, Layout> layouts;  // by (block shape, column height)
     std::map<std::string, Field> fields;
     std::map<std::vector<double>, double *> coefs;
     std::map<std::string, hipGraphExec_t> graphs;  // captured iteration chunks
@@ -192,6 +193,10 @@ RedSpec red_spec(ExecSet &S, int kind, double *dst, int nv = 1, int mode = RM_NO
 // out_p = epilogue(hop(in_{1-p})) on every active vector of the set
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int out_parity, const Field &out, const Field &in,
               const Epi &e, const RedSpec &red, hipStream_t s, bool use_active = true);
+// out_p = epi_p(hop(in_{1-p})) for both parities p (no reduction), in one launch
+// when the set is a single vector
+wl_status hop2(ExecSet &S, int prec, int recon, bool dag, const Field out[2], const Field in[2], const Epi e[2],
+               hipStream_t s, bool use_active = true);
 // bcast: bit j marks field j as a single vector shared by every vector of the set
 wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const double *s0, const RedSpec &red,
                hipStream_t s, bool use_active = true, int parity = 0, int bcast = 0);
@@ -253,6 +258,10 @@ int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream
 bool capturing(hipStream_t s);
 std::string hop_key(const ExecSet &S, int prec, int recon, bool dag);
 std::vector<int> hop_candidates(int prec);
+int cfg_make(int var, int block, int col);  // hop launch configuration: variant, block size, column height
+int cfg_var(int c);
+int cfg_block(int c);
+int cfg_col(int c);
 
 // Kernel timing of hop launches (eager launches only: a solver runs without
 // graphs while timing is on).  Each timed launch carries start/end events that

@@ -126,7 +126,16 @@ struct HopArgs {
     // one == 1: the set is a single vector (vector 0 of system 0), so a block
     // loads its descriptors without waiting for the block map
     int32_t one;
-    int32_t pad1_;
+    // twin == 1: the launch covers both output parities: logical blocks
+    // [nblocks/2, nblocks) repeat the block map for output parity 1 - parity,
+    // reading the fields of the second slot below (no reduction)
+    int32_t twin;
+    const void *in_b;
+    const float *in_norm_b;
+    void *out_b;
+    float *out_norm_b;
+    const void *X_b[4];
+    const float *Xn_b[4];
 };
 
 }  // namespace wl

@@ -83,3 +83,19 @@ def test_overlap_cg_zero_source_and_validation(case):
         w.overlap_dslash(g, to_dev(eta), x, 2, RHO, 0.1, DEG, LO, HI, scale, 0, "f16", 12)
     assert e.value.status == w.WL_ERR_PREC
     g.close()
+
+
+def test_overlap_cg_single_rhs(case):
+    """One right-hand side (the GWU-code inverter's usual call): both parities
+    of each H_W application run in one launch inside every sign evaluation."""
+    w = need_gpu()
+    U, scale = case
+    mass, tol = 0.2, 1e-10
+    eta = li.gaussian_spinor(L, 2204)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.overlap_cg(g, to_dev(eta), x, 1, RHO, mass, DEG, LO, HI, scale, tol, 2000, "f32", 12, 1e-3)
+    got = from_dev(x, eta.shape)
+    assert info[0]["converged"] == 1 and info[0]["true_resid"] <= tol, info[0]
+    assert rel(oracle.overlap(L, U, got[0], RHO, mass, DEG, LO, HI, scale), eta[0]) <= 1.5 * tol
+    g.close()

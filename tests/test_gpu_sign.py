@@ -57,3 +57,22 @@ def test_sign_automatic_scale():
     w.overlap_sign_cheb(g, to_dev(got), out2, 1, 1.5, 200, 0.003, 1.0, -1.0, "f64", 18)
     assert rel(from_dev(out2, psi.shape), psi) <= 1e-8
     g.close()
+
+
+@pytest.mark.parametrize("prec,recon,gate", [("f64", 18, 1e-12), ("f32", 12, 1e-5)])
+def test_sign_single_rhs_matches_oracle(prec, recon, gate):
+    """One right-hand side: both output parities of every H_W application run
+    in one launch.  A ragged lattice (6 x 4 x 2 x 10: 240 sites per parity)
+    leaves a partial block in each half of that launch."""
+    w = need_gpu()
+    L = (6, 4, 2, 10)
+    U = li.near_identity_links(L, 0.2, 1007)
+    psi = li.gaussian_spinor(L, 2007)
+    scale = 1.02 * oracle.hw2_lmax(L, U, 1.5, psi[0], iters=200)
+    ref = oracle.sign_cheb(L, U, psi, 1.5, 100, 0.003, 1.0, scale)
+    g = w.Gauge(L, to_dev(U))
+    out = to_dev(np.zeros_like(psi))
+    w.overlap_sign_cheb(g, to_dev(psi), out, 1, 1.5, 100, 0.003, 1.0, scale, prec, recon)
+    got = from_dev(out, psi.shape)
+    assert rel(got, ref) <= gate, rel(got, ref)
+    g.close()

@@ -1,6 +1,7 @@
 """Every launch variant the autotuner may pick for the hop (direction fence,
-occupancy target, non-temporal or cached links) x block size, pinned one at a
-time, must give the oracle's D-slash and a converging mixed-precision solve."""
+occupancy target, non-temporal or cached links) x block size x column height
+of the block order, pinned one at a time, must give the oracle's D-slash and a
+converging mixed-precision solve."""
 import os
 
 import numpy as np
@@ -16,16 +17,18 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture
 def force(monkeypatch):
-    def set_cfg(var, block):
-        monkeypatch.setenv("WL_TUNE_FORCE", str(var * 1024 + block))
+    def set_cfg(var, block, col=4):
+        monkeypatch.setenv("WL_TUNE_FORCE", "%d:%d:%d" % (var, block, col))
     return set_cfg
 
 
-@pytest.mark.parametrize("var,block", [(v, b) for v in range(6) for b in (64, 512)] + [(6, 256), (6, 512), (7, 64),
-                                                                                         (7, 256)])
-def test_every_hop_variant_matches_oracle(var, block, force):
+@pytest.mark.parametrize("var,block,col", [(v, b, 4) for v in range(6) for b in (64, 512)] +
+                         [(v, 1024, 16) for v in range(6)] + [(6, 256, 4), (6, 512, 16), (7, 64, 4), (7, 256, 16)])
+def test_every_hop_variant_matches_oracle(var, block, col, force):
+    """(1024-thread blocks exist for FP32 and half-precision storage only; for
+    FP64 the pinned configuration is not a candidate and the tuner's is used)"""
     w = need_gpu()
-    force(var, block)
+    force(var, block, col)
     L = (4, 6, 2, 8)
     U = li.haar_links(L, 41)
     psi = li.gaussian_spinor(L, 42, nrhs=3)
@@ -73,3 +76,22 @@ def test_rhs_block_variant_solves(var, block, sloppy, force):
     for r in range(5):
         tr = np.linalg.norm(eta[r] - oracle.wilson(L, U, psi[r], 0.1245)) / np.linalg.norm(eta[r])
         assert st == w.WL_OK and tr <= 1e-10, (block, sloppy, r, st, info[r], tr)
+
+
+def test_untuned_fallback_solves(monkeypatch):
+    """With tuning switched off the hop runs the fallback configuration (the
+    one also used when a hop is first met inside a graph capture); a lattice
+    no other test uses, so no tuned configuration is cached for it."""
+    w = need_gpu()
+    monkeypatch.setenv("WL_TUNE", "0")
+    L = (6, 6, 4, 10)
+    U = li.near_identity_links(L, 0.3, 1004)
+    eta = li.gaussian_spinor(L, 2004, nrhs=2)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.wilson_cg(g, to_dev(eta), x, 2, 0.1245, 1e-10, 2000, "f16", 12, 0.1, check=False)
+    psi = from_dev(x, eta.shape)
+    g.close()
+    for r in range(2):
+        tr = np.linalg.norm(eta[r] - oracle.wilson(L, U, psi[r], 0.1245)) / np.linalg.norm(eta[r])
+        assert st == w.WL_OK and tr <= 1e-10, (r, st, info[r], tr)
