@@ -33,6 +33,12 @@ namespace wl {
 //   7: each thread serves two right-hand sides of one system at its site: the
 //      neighbour index and each link (with its recon-12 row) are formed once
 //      for both; one direction in flight, 3 waves (multi-RHS sets; pair layouts)
+//   8: the waves of a block serve consecutive right-hand sides of one system on
+//      the same 64 sites (as 6), and the block's 8 x 64 links are read, rebuilt
+//      to 18 reals and stored in LDS once, together with the neighbour indices,
+//      before any wave starts its hop: no right-hand side repeats a link load,
+//      the recon-12 arithmetic or the site-coordinate arithmetic (FP32 and
+//      half-precision storage; not with the clover epilogue)
 // Variants 4 and 5 exist for FP16/BF16 storage only (FP32 and FP64 operands of
 // four directions do not fit the registers); for those they repeat variant 3.
 template <int SP, int VAR> struct HopVar {
@@ -48,7 +54,7 @@ template <int SP, int VAR> struct HopVar {
     // occupancy target already allows 4 waves per SIMD; 512 otherwise
     static constexpr int max_block = waves >= 4 && VAR < 6 ? 1024 : 512;
 };
-constexpr int kHopVariants = 8;
+constexpr int kHopVariants = 9;
 
 // The fields of the output parity a block computes: the launch's first slot,
 // or for the second half of a twin launch the second one.  X and Xn point into
@@ -246,6 +252,126 @@ void k_hop(HopArgs a)
     }
 }
 
+// Variant 8.  LDS holds, per direction d = 2 mu + (backward), the rebuilt link
+// of each of the block's 64 sites as 9 complex numbers ([d][element][site], so
+// a wave's 64 lanes read 64 consecutive float2) and the neighbour's
+// checkerboard index with the antiperiodic sign in bit 31: 38.9 KB per block.
+constexpr int kLdsLinkBytes = 8 * 9 * 64 * (int)sizeof(float2) + 8 * 64 * (int)sizeof(int);
+
+template <int GP, int R, int MU, int DIR>
+__device__ __forceinline__ void stage_dir(const SysDesc &sd, const HopSite &hs, int parity, const Site &st, int cb,
+                                          int lane, bool nt, float2 (*su)[64], int *sn)
+{
+    bool flip;
+    const int ncb = neighbour<MU, DIR>(sd, st, cb, flip);
+    cpx<float> u[3][3];
+    if (nt)
+        hop_link<GP, R, MU, DIR, true>(hs, parity, cb, ncb, u);
+    else
+        hop_link<GP, R, MU, DIR, false>(hs, parity, cb, ncb, u);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) su[k][lane] = float2{u[k / 3][k % 3].re, u[k / 3][k % 3].im};
+    sn[lane] = (int)((unsigned)ncb | (flip ? 0x80000000u : 0u));
+}
+
+template <int SP, int MU, int DIR, bool DAG>
+__device__ __forceinline__ void lds_dir(const HopSite &hs, int lane, const float2 (*su)[64], const int *sn,
+                                        float acc[24])
+{
+    constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
+    const int nn = sn[lane];
+    cpx<float> h0[3], h1[3];
+    const float f = project_neighbour<SP, MU, SG>(hs, nn & 0x7fffffff, nn < 0, h0, h1);
+    cpx<float> u[3][3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float2 w = su[k][lane];
+        u[k / 3][k % 3] = cpx<float>{w.x, w.y};
+    }
+    hop_accumulate<SP, MU, DIR, SG>(u, h0, h1, f, acc);
+}
+
+template <int SP, int GP, int R, bool DAG>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_hop_lds(HopArgs a)
+{
+    static_assert(SP != P_F64, "variant 8 stages FP32 links");
+    __shared__ float2 s_u[8][9][64];
+    __shared__ int s_n[8][64];
+    const int lb = xcd_remap(blockIdx.x, a.nblocks);
+    const int half = a.nblocks >> 1;
+    const bool second = a.twin && lb >= half;
+    const HopIO f = second ? HopIO{1 - a.parity, a.in_b, a.in_norm_b, a.out_b, a.out_norm_b, a.X_b, a.Xn_b}
+                           : HopIO{a.parity, a.in, a.in_norm, a.out, a.out_norm, a.epi.X, a.epi.Xn};
+    const BlkMap bm = a.map[second ? lb - half : lb];
+    const int lane = (int)threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int nw = (int)blockDim.x >> 6;
+    const int sys = a.vec[bm.v].sys;
+    auto live = [&](int v) { return v < a.nvec && a.vec[v].sys == sys && (!a.active || a.active[v]); };
+    // a block whose right-hand sides have all converged has nothing to do
+    bool any = false;
+    for (int k = 0; k < nw; ++k) any = any || live(bm.v + k);
+    if (!any) return;
+    const SysDesc sd = a.sys[sys];
+    const int cb = bm.lblk * 64 + lane;
+    if (a.stamps && threadIdx.x == 0) a.stamps[2 * lb] = (unsigned long long)wall_clock64();
+
+    // stage: wave w rebuilds the links of directions w, w + nw, ... (all waves
+    // take part, also those whose right-hand side is idle).  When the block
+    // holds every right-hand side of its system, no other block reads these
+    // links: they are loaded non-temporally.
+    const bool nt = a.vec[bm.v].rhs == 0 && (bm.v + nw >= a.nvec || a.vec[bm.v + nw].sys != sys);
+    if (cb < sd.Vh) {
+        const Site st = cb_coords(sd, cb, f.parity);
+        HopSite hl;
+        hl.gauge = sd.gauge;
+        hl.gstride = sd.gstride;
+        for (int d = w; d < 8; d += nw) {
+            switch (d) {
+            case 0: stage_dir<GP, R, 0, +1>(sd, hl, f.parity, st, cb, lane, nt, s_u[0], s_n[0]); break;
+            case 1: stage_dir<GP, R, 0, -1>(sd, hl, f.parity, st, cb, lane, nt, s_u[1], s_n[1]); break;
+            case 2: stage_dir<GP, R, 1, +1>(sd, hl, f.parity, st, cb, lane, nt, s_u[2], s_n[2]); break;
+            case 3: stage_dir<GP, R, 1, -1>(sd, hl, f.parity, st, cb, lane, nt, s_u[3], s_n[3]); break;
+            case 4: stage_dir<GP, R, 2, +1>(sd, hl, f.parity, st, cb, lane, nt, s_u[4], s_n[4]); break;
+            case 5: stage_dir<GP, R, 2, -1>(sd, hl, f.parity, st, cb, lane, nt, s_u[5], s_n[5]); break;
+            case 6: stage_dir<GP, R, 3, +1>(sd, hl, f.parity, st, cb, lane, nt, s_u[6], s_n[6]); break;
+            default: stage_dir<GP, R, 3, -1>(sd, hl, f.parity, st, cb, lane, nt, s_u[7], s_n[7]); break;
+            }
+        }
+    }
+    __syncthreads();
+
+    const int v = bm.v + w;
+    const bool valid = live(v);
+    double rv[3] = {0.0, 0.0, 0.0};
+    if (valid && cb < sd.Vh) {
+        const VecDesc vd = a.vec[v];
+        const HopSite hs = hop_input<SP>(a, f, vd, sd);
+        float acc[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = 0.f;
+        // two directions' operands in flight per wave, as variant 6
+        lds_dir<SP, 0, +1, DAG>(hs, lane, s_u[0], s_n[0], acc);
+        lds_dir<SP, 0, -1, DAG>(hs, lane, s_u[1], s_n[1], acc);
+        sched_fence(acc);
+        lds_dir<SP, 1, +1, DAG>(hs, lane, s_u[2], s_n[2], acc);
+        lds_dir<SP, 1, -1, DAG>(hs, lane, s_u[3], s_n[3], acc);
+        sched_fence(acc);
+        lds_dir<SP, 2, +1, DAG>(hs, lane, s_u[4], s_n[4], acc);
+        lds_dir<SP, 2, -1, DAG>(hs, lane, s_u[5], s_n[5], acc);
+        sched_fence(acc);
+        lds_dir<SP, 3, +1, DAG>(hs, lane, s_u[6], s_n[6], acc);
+        lds_dir<SP, 3, -1, DAG>(hs, lane, s_u[7], s_n[7], acc);
+        sched_fence(acc);
+        hop_epilogue<SP, false>(a, f, vd, sd, cb, acc, rv);
+    }
+    if (a.red.kind != RED_NONE && valid) wave_reduce_store_n(a.red, a.vec[v].pslot0, bm.lblk, rv);
+    if (a.stamps) {
+        __syncthreads();
+        if (threadIdx.x == 0) a.stamps[2 * lb + 1] = (unsigned long long)wall_clock64();
+    }
+}
+
 // With events, the dispatch itself records them at the kernel's start and end
 // (the kernel-timing form of the launch), so the measured interval is the
 // kernel alone.
@@ -287,11 +413,21 @@ static hipError_t launch_hop_t(int var, bool dag, bool clov, const HopArgs &a, i
     case 5: return launch_hop_v<SP, GP, R, 5>(dag, clov, a, block, s, e0, e1);
     case 6: return launch_hop_v<SP, GP, R, 6>(dag, clov, a, block, s, e0, e1);
     case 7: return launch_hop_v<SP, GP, R, 7>(dag, clov, a, block, s, e0, e1);
+    case 8:
+        if constexpr (SP != P_F64) {
+            if (clov || block % 64 != 0 || block > 1024) return hipErrorInvalidValue;
+            if (dag)
+                dispatch(k_hop_lds<SP, GP, R, true>, a, block, s, e0, e1);
+            else
+                dispatch(k_hop_lds<SP, GP, R, false>, a, block, s, e0, e1);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
 
-int hop_variants(int prec) { (void)prec; return kHopVariants; }
+int hop_variants(int prec) { return prec == P_F64 ? kHopVariants - 1 : kHopVariants; }  // no variant 8 in FP64
 
 hipError_t launch_hop(int prec, int recon, bool dag, bool clov, int var, const HopArgs &a, int block, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1)

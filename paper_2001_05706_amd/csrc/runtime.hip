@@ -135,15 +135,14 @@ int tuned_block(const std::string &key, const std::vector<int> &cands, hipStream
                 const std::function<hipError_t(int)> &run)
 {
     // WL_TUNE_FORCE=<variant>:<block>[:<column height>] pins every hop launch
-    // to one candidate (tests of each variant; column height 4 by default)
+    // whose candidates hold that variant and block size (tests of each
+    // variant; column height 4 by default, any height >= 1 accepted)
     const char *force = getenv("WL_TUNE_FORCE");
     if (force && key.compare(0, 4, "hop/") == 0) {
         int v = -1, b = -1, col = 4;
-        if (sscanf(force, "%d:%d:%d", &v, &b, &col) >= 2) {
-            const int c = cfg_make(v, b, col);
+        if (sscanf(force, "%d:%d:%d", &v, &b, &col) >= 2 && col >= 1 && col < 4096)
             for (int x : cands)
-                if (x == c) return c;
-        }
+                if (cfg_var(x) == v && cfg_block(x) == b) return cfg_make(v, b, col);
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -677,8 +676,10 @@ std::vector<int> hop_candidates(int prec)
     for (int col : {4, 16})
         for (int v = 0; v < hop_variants(prec); ++v) {
             if ((v == 4 || v == 5) && !half) continue;  // four directions in flight: half precision only
-            if (v == 6) {
-                for (int b : {256, 512}) c.push_back(cfg_make(v, b, col));  // 4 or 8 right-hand sides per block
+            // variants 6 and 8: 4 or 8 (8: also 12 or 16) right-hand sides per block
+            if (v == 6 || v == 8) {
+                for (int b : {256, 512, 768, 1024})
+                    if (v == 8 || b <= 512) c.push_back(cfg_make(v, b, col));
                 continue;
             }
             // two FP64 accumulators fit only at 2 waves per SIMD, where variant 7 measured
@@ -692,13 +693,13 @@ std::vector<int> hop_candidates(int prec)
     return c;
 }
 
-// the block layout a hop launch configuration runs on: variant 6 blocks hold
-// B / 64 right-hand sides of 64 sites each, variant 7 blocks B sites of two
-// right-hand sides
+// the block layout a hop launch configuration runs on: variant 6 and 8 blocks
+// hold B / 64 right-hand sides of 64 sites each, variant 7 blocks B sites of
+// two right-hand sides
 static wl_status hop_layout(ExecSet &S, int cfg, const Layout **L)
 {
     const int var = cfg_var(cfg), B = cfg_block(cfg);
-    return S.layout(var == 6 ? -(B / 64) : var == 7 ? kPairLayout + B : B, L, cfg_col(cfg));
+    return S.layout(var == 6 || var == 8 ? -(B / 64) : var == 7 ? kPairLayout + B : B, L, cfg_col(cfg));
 }
 
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
@@ -739,7 +740,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
     std::vector<int> cands = hop_candidates(prec);
     if (clov)  // the clover epilogue needs the registers of the two-direction variants (0 and 3)
         cands.erase(std::remove_if(cands.begin(), cands.end(),
-                                   [](int c) { return cfg_var(c) == 1 || cfg_var(c) == 2; }),
+                                   [](int c) { return cfg_var(c) == 1 || cfg_var(c) == 2 || cfg_var(c) == 8; }),
                     cands.end());
     int max_nrhs = 0;
     for (auto &e : S.systems) max_nrhs = std::max(max_nrhs, e.nrhs);
@@ -1248,7 +1249,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
     }
     const double *coef = nullptr;
     if (st == WL_OK) st = coef_table(*S, {0, 0, 0, 0, 1.0}, &coef);
-    int B = 256, cfg = 256;
+    int B = 256, cfg = cfg_make(0, 256, 4);
     const Layout *L = nullptr;
     if (st == WL_OK) {
         // tune on set 0 with the same launch the timed loop makes

@@ -23,10 +23,12 @@ def force(monkeypatch):
 
 
 @pytest.mark.parametrize("var,block,col", [(v, b, 4) for v in range(6) for b in (64, 512)] +
-                         [(v, 1024, 16) for v in range(6)] + [(6, 256, 4), (6, 512, 16), (7, 64, 4), (7, 256, 16)])
+                         [(v, 1024, 16) for v in range(6)] + [(6, 256, 4), (6, 512, 16), (7, 64, 4), (7, 256, 16)] +
+                         [(8, 256, 4), (8, 512, 16), (8, 768, 1), (8, 1024, 16)])
 def test_every_hop_variant_matches_oracle(var, block, col, force):
-    """(1024-thread blocks exist for FP32 and half-precision storage only; for
-    FP64 the pinned configuration is not a candidate and the tuner's is used)"""
+    """(1024-thread blocks and variant 8 exist for FP32 and half-precision
+    storage only; for FP64 the pinned configuration is not a candidate and the
+    tuner's is used)"""
     w = need_gpu()
     force(var, block, col)
     L = (4, 6, 2, 8)
@@ -56,13 +58,16 @@ def test_every_hop_variant_solves(var, sloppy, force):
     assert st == w.WL_OK and tr <= 1e-10, (var, sloppy, st, info, tr)
 
 
-@pytest.mark.parametrize("var,block", [(6, 256), (6, 512), (7, 64), (7, 256)])
+@pytest.mark.parametrize("var,block", [(6, 256), (6, 512), (7, 64), (7, 256), (8, 256), (8, 512), (8, 768),
+                                       (8, 1024)])
 @pytest.mark.parametrize("sloppy", ["f32", "f16"])
 def test_rhs_block_variant_solves(var, block, sloppy, force):
-    """variant 6 (the waves of a block serve consecutive right-hand sides) and 7
-    (each thread serves two right-hand sides): 5 right-hand sides, so the last
-    block of 4 or 8, or the last pair, is partly empty; converged right-hand
-    sides drop out one by one"""
+    """variants 6 and 8 (the waves of a block serve consecutive right-hand
+    sides; 8 with the block's links staged in LDS) and 7 (each thread serves
+    two right-hand sides): 5 right-hand sides, so the last block of 4, 8, 12 or
+    16, or the last pair, is partly empty; converged right-hand sides drop out
+    one by one (a variant 8 block whose right-hand sides have all converged
+    returns before staging)"""
     w = need_gpu()
     force(var, block)
     L = (8, 8, 8, 8)
