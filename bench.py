@@ -275,23 +275,35 @@ def dslash_sets(w, prec, recon, nrhs, vh):
     return min(n, 16), per_set
 
 
-def bench_dslash(w, torch, li, dev, a, g32, g24, g24b):
+DSLASH_CASES = [("32", "f16", 12, 1), ("32", "f32", 12, 1), ("32", "bf16", 12, 1), ("32", "f64", 18, 1),
+                ("24", "f64", 18, 1), ("24", "f64", 12, 1), ("24", "f32", 18, 1), ("24", "f32", 12, 1),
+                ("24", "f16", 12, 1), ("24b", "f32", 12, 12), ("24b", "f16", 12, 12)]
+DSLASH_LATTICE = {"32": (32, 32, 32, 64), "24": (24, 24, 24, 48), "24b": (24, 24, 24, 48)}
+
+
+def dslash_tag(lat, prec, rc, nrhs):
+    L = DSLASH_LATTICE[lat]
+    return "%dc%d_%s_r%d%s" % (L[0], L[3], prec, rc, "" if nrhs == 1 else "_%drhs" % nrhs)
+
+
+def bench_dslash(w, torch, li, dev, a, gauges, only=None, protocols=("warm", "cold")):
     """Stand-alone single-parity hops (D-slash) in the warm (operands reused,
-    as inside a solver) and cold (rotated operand sets) protocols."""
+    as inside a solver) and cold (rotated operand sets) protocols.  gauges maps
+    "32", "24" and "24b" (a second 24^3x48 handle for the multi-RHS cases) to
+    gauge handles; `only`, if given, is the set of case tags to run."""
     ds = {}
     stream = torch.cuda.current_stream()
-    cases = [(g32, (32, 32, 32, 64), "f16", 12, 1), (g32, (32, 32, 32, 64), "f32", 12, 1),
-             (g32, (32, 32, 32, 64), "bf16", 12, 1), (g32, (32, 32, 32, 64), "f64", 18, 1),
-             (g24, (24, 24, 24, 48), "f64", 18, 1), (g24, (24, 24, 24, 48), "f64", 12, 1),
-             (g24, (24, 24, 24, 48), "f32", 18, 1), (g24, (24, 24, 24, 48), "f32", 12, 1),
-             (g24, (24, 24, 24, 48), "f16", 12, 1),
-             (g24b, (24, 24, 24, 48), "f32", 12, 12), (g24b, (24, 24, 24, 48), "f16", 12, 12)]
-    for g, L, prec, rc, nrhs in cases:
+    for lat, prec, rc, nrhs in DSLASH_CASES:
+        tag = dslash_tag(lat, prec, rc, nrhs)
+        if only is not None and tag not in only:
+            continue
+        g, L = gauges[lat], DSLASH_LATTICE[lat]
         vh = int(np.prod(L)) // 2
         bps = nrhs * w.wl_hop_bytes_per_site(prec, rc, nrhs)
-        tag = "%dc%d_%s_r%d%s" % (L[0], L[3], prec, rc, "" if nrhs == 1 else "_%drhs" % nrhs)
         nsets, per_set = dslash_sets(w, prec, rc, nrhs, vh)
         for ns, name in [(1, "warm"), (nsets, "cold")]:
+            if name not in protocols:
+                continue
             try:
                 sec = w.wl_bench_dslash(g, prec, rc, nrhs, 0, ns, 100 if nrhs == 1 else 20, stream)
             except w.WilsonError as e:
@@ -374,6 +386,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip every side measurement")
     ap.add_argument("--extras", default="cg,c2,dslash,batch,uneven,sign,overlap,clover",
                     help="side measurements outside the timed region (comma list)")
+    ap.add_argument("--dslash-only", default=None,
+                    help="run only these D-slash cases (comma list of tags such as 24c48_f32_r12_12rhs, warm "
+                         "protocol) and print their results: for counter profiles of one kernel")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -386,6 +401,24 @@ def main():
 
     w.lib()
     dev = torch.device("cuda:0")
+    if a.dslash_only:
+        only = set(a.dslash_only.split(","))
+        known = {dslash_tag(*c) for c in DSLASH_CASES}
+        if not only <= known:
+            print("unknown D-slash case(s) %s; known: %s" % (sorted(only - known), sorted(known)), file=sys.stderr)
+            return 2
+        gauges = {}
+        for lat, seed in (("32", 1003), ("24", 1002), ("24b", 1002)):
+            if any(dslash_tag(*c) in only for c in DSLASH_CASES if c[0] == lat):
+                gauges[lat] = w.Gauge(DSLASH_LATTICE[lat], _dev(torch, li.near_identity_links(
+                    DSLASH_LATTICE[lat], 0.3, seed), dev))
+        try:
+            ds = bench_dslash(w, torch, li, dev, a, gauges, only, ("warm",))
+        finally:
+            for g in gauges.values():
+                g.close()
+        print(json.dumps({"dslash": ds}), flush=True)
+        return 0
     L = (32, 32, 32, 64)
     vh = int(np.prod(L)) // 2
     kappa, tol, maxiter = 0.1248, 1e-10, 5000
@@ -524,7 +557,7 @@ def main():
             g24 = w.Gauge((24, 24, 24, 48), _dev(torch, U24, dev))
             g24b = w.Gauge((24, 24, 24, 48), _dev(torch, U24, dev))
             try:
-                return bench_dslash(w, torch, li, dev, a, g, g24, g24b)
+                return bench_dslash(w, torch, li, dev, a, {"32": g, "24": g24, "24b": g24b})
             finally:
                 g24.close()
                 g24b.close()
