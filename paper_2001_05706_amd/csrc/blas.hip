@@ -51,7 +51,7 @@ template <int P> __device__ __forceinline__ const void *fbase(const BlasArgs &a,
     return (a.bcast >> j) & 1 ? a.f[j] : vbase<P>(a.f[j], vd);
 }
 
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -60,23 +60,23 @@ __global__ __launch_bounds__(256) void k_cg_update(BlasArgs a)
     if (live) {
         const T al = (T)a.s0[vi];
         T x[24], p[24], r[24], q[24];
-        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
-        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, p);
-        load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
-        load_spinor<P>(vbase<P>(a.f[3], vd), nbase(a.fn[3], vd), sd.stride, cb, q);
+        load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, p);
+        load_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
+        load_spinor<P, NT>(vbase<P>(a.f[3], vd), nbase(a.fn[3], vd), sd.stride, cb, q);
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
             x[k] += al * p[k];
             r[k] -= al * q[k];
         }
-        store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
-        store_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
+        store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        store_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, r);
         nrm = site_norm2(r);
     }
     if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_xpay(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -84,16 +84,16 @@ __global__ __launch_bounds__(256) void k_xpay(BlasArgs a)
     if (!live) return;
     const T be = (T)a.s0[vi];
     T p[24], s[24];
-    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
-    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
+    load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
 #pragma unroll
     for (int k = 0; k < 24; ++k) p[k] = s[k] + be * p[k];
-    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
 // CGNR with the solution update folded into the direction update: the
 // residual step alone here, x += alpha p with p = s + beta p below
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -102,17 +102,17 @@ __global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
     if (live) {
         const T al = (T)a.s0[vi];
         T r[24], q[24];
-        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
-        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, q);
+        load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+        load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, q);
 #pragma unroll
         for (int k = 0; k < 24; ++k) r[k] -= al * q[k];
-        store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+        store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
         nrm = site_norm2(r);
     }
     if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
 }
 
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -121,16 +121,16 @@ __global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
     const T be = (T)a.s0[vi];
     const T al = (T)a.sc[SC_ALPHA * a.nvec + vi];
     T p[24], s[24], x[24];
-    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
-    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
-    load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
+    load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, s);
+    load_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
 #pragma unroll
     for (int k = 0; k < 24; ++k) {
         x[k] += al * p[k];
         p[k] = s[k] + be * p[k];
     }
-    store_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
-    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    store_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
+    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
 template <int P, bool ONE = false>
@@ -228,7 +228,7 @@ template <class T> __device__ __forceinline__ void cmul_site(T zr, T zi, const T
     }
 }
 
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -245,19 +245,19 @@ __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
     const double q2r = (ar * orr + ai * oi) / d2, q2i = (ai * orr - ar * oi) / d2;
     const T br = (T)(q1r * q2r - q1i * q2i), bi = (T)(q1r * q2i + q1i * q2r);
     T p[24], r[24], v[24], t[24];
-    load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
-    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
-    load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
+    load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
+    load_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
     cmul_site((T)orr, (T)oi, v, t);  // omega v
 #pragma unroll
     for (int k = 0; k < 24; ++k) t[k] = p[k] - t[k];
     cmul_site(br, bi, t, p);  // beta (p - omega v)
 #pragma unroll
     for (int k = 0; k < 24; ++k) p[k] += r[k];
-    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -266,15 +266,15 @@ __global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
     double ar, ai;
     cscal(a, SC_AL_RE, vi, ar, ai);
     T r[24], v[24], av[24];
-    load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
-    load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
+    load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);
+    load_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, v);
     cmul_site((T)ar, (T)ai, v, av);
 #pragma unroll
     for (int k = 0; k < 24; ++k) r[k] -= av[k];
-    store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
 }
 
-template <int P, bool ONE = false>
+template <int P, bool ONE = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_bicg_xr(BlasArgs a)
 {
     using T = typename SpinorFmt<P>::real;
@@ -285,22 +285,22 @@ __global__ __launch_bounds__(256) void k_bicg_xr(BlasArgs a)
         cscal(a, SC_AL_RE, vi, ar, ai);
         cscal(a, SC_OM_RE, vi, orr, oi);
         T x[24], y[24], z[24], w[24];
-        load_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
-        load_spinor<P>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, y);  // p
+        load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, y);  // p
         cmul_site((T)ar, (T)ai, y, z);
 #pragma unroll
         for (int k = 0; k < 24; ++k) x[k] += z[k];
-        load_spinor<P>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, y);  // s
+        load_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, y);  // s
         cmul_site((T)orr, (T)oi, y, z);
 #pragma unroll
         for (int k = 0; k < 24; ++k) x[k] += z[k];
-        store_spinor<P>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
-        load_spinor<P>(vbase<P>(a.f[4], vd), nbase(a.fn[4], vd), sd.stride, cb, w);  // t
+        store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, x);
+        load_spinor<P, NT>(vbase<P>(a.f[4], vd), nbase(a.fn[4], vd), sd.stride, cb, w);  // t
         cmul_site((T)orr, (T)oi, w, z);
 #pragma unroll
         for (int k = 0; k < 24; ++k) y[k] -= z[k];  // r = s - omega t
-        store_spinor<P>(vbase<P>(a.f[3], vd), nbase(a.fn[3], vd), sd.stride, cb, y);
-        load_spinor<P>(vbase<P>(a.f[5], vd), nbase(a.fn[5], vd), sd.stride, cb, w);  // rhat
+        store_spinor<P, NT>(vbase<P>(a.f[3], vd), nbase(a.fn[3], vd), sd.stride, cb, y);
+        load_spinor<P, NT>(vbase<P>(a.f[5], vd), nbase(a.fn[5], vd), sd.stride, cb, w);  // rhat
         site_cdot(w, y, rv[0], rv[1]);
         rv[2] = site_norm2(y);
     }
@@ -413,51 +413,44 @@ __global__ __launch_bounds__(256) void k_convert(BlasArgs a)
     store_spinor<PD>(vbase<PD>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, y);
 }
 
+// Solver-iteration kernels come in four instantiations: one-vector sets (see
+// WL_BLAS_PROLOGUE) and streamed fields.  Their field accesses carry the
+// non-temporal hint when the set's fields are large against the 256 MB
+// last-level cache (ExecSet::stream_fields): each field is streamed once per
+// launch, and without the hint it displaces the links, which the four hops of
+// an iteration re-read from that cache.
+#define WL_LAUNCH_ITER(K)                                                     \
+    do {                                                                      \
+        if (a.one && a.stream) hipLaunchKernelGGL((K<P, true, true>), g, b, 0, s, a); \
+        else if (a.one) hipLaunchKernelGGL((K<P, true, false>), g, b, 0, s, a);      \
+        else if (a.stream) hipLaunchKernelGGL((K<P, false, true>), g, b, 0, s, a);   \
+        else hipLaunchKernelGGL((K<P, false, false>), g, b, 0, s, a);                \
+    } while (0)
+
 template <int P>
 static hipError_t launch_blas_t(int op, const BlasArgs &a, int block, hipStream_t s)
 {
     dim3 g(a.nblocks), b(block);
     switch (op) {
-    case BL_CG_UPDATE:
-        if (a.one) hipLaunchKernelGGL((k_cg_update<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_cg_update<P>, g, b, 0, s, a);
-        break;
-    case BL_XPAY:
-        if (a.one) hipLaunchKernelGGL((k_xpay<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_xpay<P>, g, b, 0, s, a);
-        break;
+    case BL_CG_UPDATE: WL_LAUNCH_ITER(k_cg_update); break;
+    case BL_XPAY: WL_LAUNCH_ITER(k_xpay); break;
     case BL_ACCUM: hipLaunchKernelGGL(k_accum<P>, g, b, 0, s, a); break;
     case BL_NORM2: hipLaunchKernelGGL(k_norm2<P>, g, b, 0, s, a); break;
     case BL_ZERO: hipLaunchKernelGGL(k_zero<P>, g, b, 0, s, a); break;
     case BL_COPY: hipLaunchKernelGGL((k_convert<P, P>), g, b, 0, s, a); break;
     case BL_FILL: hipLaunchKernelGGL(k_fill<P>, g, b, 0, s, a); break;
     case BL_SCALE_RSQRT: hipLaunchKernelGGL(k_scale_rsqrt<P>, g, b, 0, s, a); break;
-    case BL_BICG_P:
-        if (a.one) hipLaunchKernelGGL((k_bicg_p<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_bicg_p<P>, g, b, 0, s, a);
-        break;
-    case BL_BICG_S:
-        if (a.one) hipLaunchKernelGGL((k_bicg_s<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_bicg_s<P>, g, b, 0, s, a);
-        break;
-    case BL_BICG_XR:
-        if (a.one) hipLaunchKernelGGL((k_bicg_xr<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_bicg_xr<P>, g, b, 0, s, a);
-        break;
+    case BL_BICG_P: WL_LAUNCH_ITER(k_bicg_p); break;
+    case BL_BICG_S: WL_LAUNCH_ITER(k_bicg_s); break;
+    case BL_BICG_XR: WL_LAUNCH_ITER(k_bicg_xr); break;
     case BL_CDOT: hipLaunchKernelGGL(k_cdot<P>, g, b, 0, s, a); break;
     case BL_G5COPY: hipLaunchKernelGGL(k_g5copy<P>, g, b, 0, s, a); break;
     case BL_CLOV_INV: hipLaunchKernelGGL(k_clov_inv<P>, g, b, 0, s, a); break;
     case BL_CAXPY: hipLaunchKernelGGL((k_caxpy<P, false>), g, b, 0, s, a); break;
     case BL_CAXPY_G5: hipLaunchKernelGGL((k_caxpy<P, true>), g, b, 0, s, a); break;
     case BL_ROT: hipLaunchKernelGGL(k_rot<P>, g, b, 0, s, a); break;
-    case BL_R_UPDATE:
-        if (a.one) hipLaunchKernelGGL((k_r_update<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_r_update<P>, g, b, 0, s, a);
-        break;
-    case BL_XPAY_X:
-        if (a.one) hipLaunchKernelGGL((k_xpay_x<P, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL(k_xpay_x<P>, g, b, 0, s, a);
-        break;
+    case BL_R_UPDATE: WL_LAUNCH_ITER(k_r_update); break;
+    case BL_XPAY_X: WL_LAUNCH_ITER(k_xpay_x); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

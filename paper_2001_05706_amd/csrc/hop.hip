@@ -70,6 +70,24 @@ struct HopIO {
     const float *const *Xn;
 };
 
+// Epilogue field X[j] at site cb, before its half-precision norm is applied.
+// Each X field is read once per launch; for sets whose fields are large
+// against the last-level cache the read is non-temporal, so that it does not
+// push out the links that the solver's next hops re-read from that cache.
+template <int SP>
+__device__ __forceinline__ void load_x(const HopArgs &a, const HopIO &f, int j, size_t voff, const VecDesc &vd,
+                                       const SysDesc &sd, int cb, typename SpinorFmt<SP>::real x[24],
+                                       typename SpinorFmt<SP>::real *nx)
+{
+    using CH = typename SpinorFmt<SP>::chunk;
+    const CH *base = (const CH *)f.X[j] + voff;
+    const float *nrm = f.Xn[j] ? f.Xn[j] + vd.site_off : nullptr;
+    if (a.stream)
+        load_spinor_raw<SP, true>(base, nrm, sd.stride, cb, x, nx);
+    else
+        load_spinor_raw<SP, false>(base, nrm, sd.stride, cb, x, nx);
+}
+
 // Everything after the hopping sum at one output site of one vector: the
 // linear-combination epilogue, the store, and the site's reduction values.
 // acc holds H psi (FP16/BF16: already multiplied by the system's c).
@@ -107,9 +125,7 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const HopIO &f, c
                 raw = false;
             }
         }
-        if (raw)
-            load_spinor_raw<SP>((const CH *)f.X[0] + voff, f.Xn[0] ? f.Xn[0] + vd.site_off : nullptr,
-                                sd.stride, cb, x, &n0);
+        if (raw) load_x<SP>(a, f, 0, voff, vd, sd, cb, x, &n0);
         const T s0 = (T)cf[0] * n0;
 #pragma unroll
         for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], s0, acc[k]);
@@ -127,8 +143,7 @@ __device__ __forceinline__ void hop_epilogue(const HopArgs &a, const HopIO &f, c
     }
     for (int j = 1; j < a.epi.nx; ++j) {
         T x[24], nj;
-        load_spinor_raw<SP>((const CH *)f.X[j] + voff, f.Xn[j] ? f.Xn[j] + vd.site_off : nullptr,
-                            sd.stride, cb, x, &nj);
+        load_x<SP>(a, f, j, voff, vd, sd, cb, x, &nj);
         const T sj = (T)cf[j] * nj;
 #pragma unroll
         for (int k = 0; k < 24; ++k) o[k] = fmadd(x[k], sj, o[k]);

@@ -731,6 +731,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
         }
         a.red = rs;
         a.one = S.nvec == 1;
+        a.stream = S.stream_fields(prec);
         return a;
     };
     // tuned per epilogue shape: a hop that also reads X fields and reduces may
@@ -843,6 +844,7 @@ wl_status hop2(ExecSet &S, int prec, int recon, bool dag, const Field out[2], co
         }
         a.red = no_red();
         a.one = 1;
+        a.stream = S.stream_fields(prec);
         a.twin = 1;
         a.in_b = in[0].p;
         a.in_norm_b = in[0].n;
@@ -891,6 +893,7 @@ wl_status blas(ExecSet &S, int op, int prec, const Field *f, int nf, const doubl
     a.sc = S.sc;
     a.nvec = S.nvec;
     a.one = S.nvec == 1;
+    a.stream = S.stream_fields(prec);
     a.red = red;
     a.parity = parity;
     a.bcast = bcast;
@@ -1281,6 +1284,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
             a.epi.coef = coef;
             a.red = no_red();
             a.one = S->nvec == 1;  // as the solvers launch it
+            a.stream = S->stream_fields(prec);
             return launch_hop(prec, recon, false, false, cfg_var(cfg), a, B, s);
         };
         for (int k = 0; k < nsets && st == WL_OK; ++k)

@@ -227,6 +227,22 @@ WL_HD uint2 ld_stream(const WL_G uint2 *p)
     const nt_u2 v = WL_NT_LOAD(nt_u2, p);
     return uint2{v.x, v.y};
 }
+WL_HD uint4 ld_stream(const WL_G uint4 *p)
+{
+    const nt_u4 v = WL_NT_LOAD(nt_u4, p);
+    return uint4{v.x, v.y, v.z, v.w};
+}
+WL_HD float ld_stream(const WL_G float *p) { return WL_NT_LOAD(float, p); }
+
+// load of a field element: plain, or with the non-temporal hint for fields
+// read once per launch
+template <bool NT, class CH> WL_HD CH ld_field(const WL_G CH *p)
+{
+    if constexpr (NT)
+        return ld_stream(p);
+    else
+        return *p;
+}
 
 // The address of a row base held in scalar registers.  `base` must be the
 // same in every lane of the wave (every kernel here takes its field bases from
@@ -260,7 +276,8 @@ template <class CH> WL_HD WL_G CH *row_elem(void *base, int c, int stride, int c
 }
 
 // 24 reals of one site of one vector.  base points at chunk 0 of the vector.
-template <int P>
+// NT: non-temporal loads (a field streamed once by the launch).
+template <int P, bool NT = false>
 WL_HD void load_spinor(const void *base, const float *norm, int stride, int cb,
                        typename SpinorFmt<P>::real v[24])
 {
@@ -269,24 +286,24 @@ WL_HD void load_spinor(const void *base, const float *norm, int stride, int cb,
     if constexpr (P == P_F64) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            double2 w = *row_elem<CH>(base, c, stride, cb);
+            double2 w = ld_field<NT>(row_elem<CH>(base, c, stride, cb));
             v[2 * c] = w.x;
             v[2 * c + 1] = w.y;
         }
     } else if constexpr (P == P_F32) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            float4 w = *row_elem<CH>(base, c, stride, cb);
+            float4 w = ld_field<NT>(row_elem<CH>(base, c, stride, cb));
             v[4 * c] = w.x;
             v[4 * c + 1] = w.y;
             v[4 * c + 2] = w.z;
             v[4 * c + 3] = w.w;
         }
     } else {
-        const float nrm = *row_elem<float>(norm, 0, 0, cb);
+        const float nrm = ld_field<NT>(row_elem<float>(norm, 0, 0, cb));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            uint4 w = *row_elem<CH>(base, c, stride, cb);
+            uint4 w = ld_field<NT>(row_elem<CH>(base, c, stride, cb));
             uint32_t q[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -298,14 +315,14 @@ WL_HD void load_spinor(const void *base, const float *norm, int stride, int cb,
 }
 
 // The 12 packed complex words of a half-precision site and its norm.
-template <int P>
+template <int P, bool NT = false>
 WL_HD void load_spinor_words(const void *base, const float *norm, int stride, int cb, uint32_t q[12], float *nrm)
 {
     using CH = typename SpinorFmt<P>::chunk;
-    *nrm = *row_elem<float>(norm, 0, 0, cb);
+    *nrm = ld_field<NT>(row_elem<float>(norm, 0, 0, cb));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        uint4 w = *row_elem<CH>(base, c, stride, cb);
+        uint4 w = ld_field<NT>(row_elem<CH>(base, c, stride, cb));
         q[4 * c] = w.x;
         q[4 * c + 1] = w.y;
         q[4 * c + 2] = w.z;
@@ -317,17 +334,17 @@ WL_HD void load_spinor_words(const void *base, const float *norm, int stride, in
 // norm in *nrm (FP64/FP32: the values themselves and 1).  A caller folds the
 // norm into a per-site coefficient; FP16 values then enter mixed-precision fmas
 // directly.
-template <int P>
+template <int P, bool NT = false>
 WL_HD void load_spinor_raw(const void *base, const float *norm, int stride, int cb,
                            typename SpinorFmt<P>::real v[24], typename SpinorFmt<P>::real *nrm)
 {
     if constexpr (P == P_F64 || P == P_F32) {
-        load_spinor<P>(base, norm, stride, cb, v);
+        load_spinor<P, NT>(base, norm, stride, cb, v);
         *nrm = 1;
     } else {
         uint32_t q[12];
         float n;
-        load_spinor_words<P>(base, norm, stride, cb, q, &n);
+        load_spinor_words<P, NT>(base, norm, stride, cb, q, &n);
         *nrm = n;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {

@@ -127,6 +127,16 @@ public:
     int nvec = 0;
     size_t total_sites = 0;    // sum of strides over vectors
 
+    // The set's fields at precision prec are large against the 256 MB
+    // last-level cache: eight of them (about what a solver iteration touches
+    // besides the links) exceed it.  The iteration kernels then read and write
+    // fields non-temporally, which keeps the links in that cache for the hops.
+    bool stream_fields(int prec) const
+    {
+        const double site = (double)nchunks(prec) * chunk_bytes(prec) + (prec == P_F16 || prec == P_BF16 ? 4 : 0);
+        return 8.0 * (double)total_sites * site > 256.0 * 1024 * 1024;
+    }
+
     // device tables: prec < 0 geometry only; recon 0: no links (geometry and clover term)
     wl_status sys_table(int prec, int recon, hipStream_t s, const SysDesc **out);
     // B > 0: blocks of B sites of one vector; B < 0: blocks of -B vectors on 64

@@ -19,7 +19,7 @@ struct BlasArgs {
     int32_t nvec;
     int32_t bcast;     // bit j: field j is one vector shared by every vector of the set
     int32_t one;       // the set holds one vector (its descriptors are at index 0)
-    int32_t pad_;
+    int32_t stream;    // solver-iteration kernels: fields read and written non-temporally
     RedSpec red;
 };
 

@@ -113,7 +113,7 @@ struct HopArgs {
     int32_t nblocks;
     int32_t parity;         // output parity
     int32_t nvec;           // vectors of the set
-    int32_t pad_;
+    int32_t stream;         // epilogue X fields read non-temporally
     const void *in;         // field bases (all vectors of the set)
     const float *in_norm;
     void *out;
