@@ -331,7 +331,9 @@ def cpu_model():
 def cpu_baseline(w, L, U, eta, kappa, tol, a):
     """The FP64 oracle on a bounded sample of the headline workload: a capped
     number of CGNR iterations with every host thread (setup and true residual
-    included), and single-parity hops with every thread and with one."""
+    included), and single-parity hops with every thread and with one; and a
+    sample of the sign-function workload."""
+    import lattice_inputs as li
     import oracle
 
     vh = int(np.prod(L)) // 2
@@ -368,6 +370,19 @@ def cpu_baseline(w, L, U, eta, kappa, tol, a):
         "dslash_one_thread": {"ms": round(hop_one * 1e3, 1), "GBs": round(hop_b / hop_one / 1e9, 3),
                               "GFLOPs": round(1320 * vh / hop_one / 1e9, 2), "threads": 1},
     }
+    # the sign-function workload (16^3 x 32, rho 1.5), sampled: one right-hand
+    # side at degree 10 (21 H_W applications) instead of 12 at degree 200
+    # (403 each); per H_W application, and the time the full workload would take
+    Ls = (16, 16, 16, 32)
+    Us = li.near_identity_links(Ls, 0.2, 1005)
+    vs = li.gaussian_spinor(Ls, 2005)
+    t0 = time.perf_counter()
+    oracle.sign_cheb(Ls, Us, vs, 1.5, 10, 0.003, 1.0, 42.25)
+    ts = time.perf_counter() - t0
+    r["sign_function_16c32_sample"] = {
+        "sample": "1 rhs, degree 10 (21 H_W applications), %d threads" % nthreads,
+        "ms": round(ts * 1e3, 1), "ms_per_hw_application": round(ts * 1e3 / 21, 2),
+        "full_workload_estimate_s": round(ts / 21 * 403 * 12, 1)}
     log("cpu oracle: %s" % r)
     return r
 
