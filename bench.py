@@ -395,7 +395,7 @@ def main():
     ap.add_argument("--sloppy", default="f16", choices=["f64", "f32", "f16", "bf16"])
     ap.add_argument("--recon", type=int, default=12)
     ap.add_argument("--delta", type=float, default=0.1)
-    ap.add_argument("--cpu-iters", type=int, default=6,
+    ap.add_argument("--cpu-iters", type=int, default=20,
                     help="cap on the oracle CG iterations timed for the CPU baseline (a bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip every side measurement")

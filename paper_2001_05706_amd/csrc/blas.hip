@@ -218,13 +218,15 @@ __device__ __forceinline__ void cscal(const BlasArgs &a, int re_slot, int v, dou
     im = a.sc[(size_t)(re_slot + 1) * a.nvec + v];
 }
 
-// y = z * x for complex z and a site of 12 complex numbers
+// y = z * x for complex z and a site of 12 complex numbers.  The fused
+// multiply-adds are written out, so that the streamed and plain
+// instantiations of a kernel round alike.
 template <class T> __device__ __forceinline__ void cmul_site(T zr, T zi, const T x[24], T y[24])
 {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        y[2 * k] = zr * x[2 * k] - zi * x[2 * k + 1];
-        y[2 * k + 1] = zr * x[2 * k + 1] + zi * x[2 * k];
+        y[2 * k] = fmadd(zr, x[2 * k], -(zi * x[2 * k + 1]));
+        y[2 * k + 1] = fmadd(zr, x[2 * k + 1], zi * x[2 * k]);
     }
 }
 
@@ -239,11 +241,11 @@ __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
     cscal(a, SC_RHOP_RE, vi, pr, pi);
     cscal(a, SC_AL_RE, vi, ar, ai);
     cscal(a, SC_OM_RE, vi, orr, oi);
-    // beta = (rho / rho_prev) (alpha / omega)
-    const double d1 = pr * pr + pi * pi, d2 = orr * orr + oi * oi;
-    const double q1r = (rr * pr + ri * pi) / d1, q1i = (ri * pr - rr * pi) / d1;
-    const double q2r = (ar * orr + ai * oi) / d2, q2i = (ai * orr - ar * oi) / d2;
-    const T br = (T)(q1r * q2r - q1i * q2i), bi = (T)(q1r * q2i + q1i * q2r);
+    // beta = (rho / rho_prev) (alpha / omega), fused multiply-adds written out
+    const double d1 = fma(pr, pr, pi * pi), d2 = fma(orr, orr, oi * oi);
+    const double q1r = fma(rr, pr, ri * pi) / d1, q1i = fma(ri, pr, -(rr * pi)) / d1;
+    const double q2r = fma(ar, orr, ai * oi) / d2, q2i = fma(ai, orr, -(ar * oi)) / d2;
+    const T br = (T)fma(q1r, q2r, -(q1i * q2i)), bi = (T)fma(q1r, q2i, q1i * q2r);
     T p[24], r[24], v[24], t[24];
     load_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
     load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, r);

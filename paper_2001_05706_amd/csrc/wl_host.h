@@ -4,6 +4,7 @@
 #pragma once
 
 #include <complex>
+#include <cstdlib>
 #include <functional>
 #include <map>
 #include <memory>
@@ -131,8 +132,11 @@ public:
     // last-level cache: eight of them (about what a solver iteration touches
     // besides the links) exceed it.  The iteration kernels then read and write
     // fields non-temporally, which keeps the links in that cache for the hops.
+    // WL_STREAM_FIELDS=0 or 1 overrides the choice (tests of both forms).
     bool stream_fields(int prec) const
     {
+        const char *env = getenv("WL_STREAM_FIELDS");
+        if (env && (env[0] == '0' || env[0] == '1')) return env[0] == '1';
         const double site = (double)nchunks(prec) * chunk_bytes(prec) + (prec == P_F16 || prec == P_BF16 ? 4 : 0);
         return 8.0 * (double)total_sites * site > 256.0 * 1024 * 1024;
     }

@@ -177,11 +177,16 @@ __device__ __forceinline__ void wave_reduce_store_n(const RedSpec &r, int pslot0
 // <a, b> = sum conj(a) b over one site (12 complex numbers)
 template <class T> __device__ __forceinline__ void site_cdot(const T a[24], const T b[24], double &re, double &im)
 {
+    // explicit fused multiply-adds: every instantiation rounds alike (left to
+    // the compiler, which of two products gets fused can differ between
+    // instantiations of the same source)
     T sr = 0, si = 0;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        sr += a[2 * k] * b[2 * k] + a[2 * k + 1] * b[2 * k + 1];
-        si += a[2 * k] * b[2 * k + 1] - a[2 * k + 1] * b[2 * k];
+        sr = fmadd(a[2 * k], b[2 * k], sr);
+        sr = fmadd(a[2 * k + 1], b[2 * k + 1], sr);
+        si = fmadd(a[2 * k], b[2 * k + 1], si);
+        si = fmadd(-a[2 * k + 1], b[2 * k], si);
     }
     re = (double)sr;
     im = (double)si;

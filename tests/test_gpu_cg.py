@@ -257,6 +257,38 @@ def test_graph_replay_matches_eager(method, monkeypatch):
     assert np.array_equal(xg, xe)
 
 
+@pytest.mark.parametrize("method", ["cgnr", "bicgstab"])
+@pytest.mark.parametrize("sloppy", ["f32", "f16"])
+def test_streamed_fields_match_plain(method, sloppy, monkeypatch):
+    """The solver-iteration kernels read and write fields non-temporally when
+    the set is large against the last-level cache; the hint changes where
+    data is cached, never a value: forced on and forced off
+    (WL_STREAM_FIELDS), a solve gives bit-identical solutions and schedules."""
+    w = need_gpu()
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1002)
+    eta = li.gaussian_spinor(L, 2004, nrhs=2)
+
+    def run():
+        g = w.Gauge(L, to_dev(U))
+        x = to_dev(np.zeros_like(eta))
+        fn = w.wilson_cg if method == "cgnr" else w.wilson_bicgstab
+        _, info = fn(g, to_dev(eta), x, 2, 0.1245, 1e-10, 2000, sloppy, 12, 0.1)
+        out = from_dev(x, eta.shape)
+        g.close()
+        return out, [(i["iters"], i["reliable_updates"], i["converged"]) for i in info]
+
+    monkeypatch.setenv("WL_STREAM_FIELDS", "0")
+    xp, ip = run()
+    monkeypatch.setenv("WL_STREAM_FIELDS", "1")
+    xs, is_ = run()
+    assert ip == is_, (ip, is_)
+    assert all(c for _, _, c in ip)
+    assert np.array_equal(xp, xs)
+    tr = true_resid(L, U, eta, xs, 0.1245)
+    assert np.all(tr <= 1e-10), tr
+
+
 @pytest.mark.parametrize("sloppy", ["bf16", "f16"])
 def test_stagnation_raises_the_sloppy_precision(sloppy):
     """With delta = 0.9 a reliable update follows every 10% fall of the sloppy

@@ -76,3 +76,32 @@ def test_sign_single_rhs_matches_oracle(prec, recon, gate):
     got = from_dev(out, psi.shape)
     assert rel(got, ref) <= gate, rel(got, ref)
     g.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_sign_streamed_fields_match_plain(nrhs, monkeypatch):
+    """The hops' epilogue fields are read non-temporally for sets large
+    against the last-level cache; forced on and forced off (WL_STREAM_FIELDS)
+    the sign function gives bit-identical results (one right-hand side runs
+    the two-parity launches, three the per-parity ones)."""
+    w = need_gpu()
+    L = (4, 4, 4, 8)
+    U = li.near_identity_links(L, 0.2, 1005)
+    psi = li.gaussian_spinor(L, 2006, nrhs=nrhs)
+    scale = 1.02 * oracle.hw2_lmax(L, U, 1.5, psi[0], iters=200)
+
+    def run():
+        g = w.Gauge(L, to_dev(U))
+        out = to_dev(np.zeros_like(psi))
+        w.overlap_sign_cheb(g, to_dev(psi), out, nrhs, 1.5, 60, 0.003, 1.0, scale, "f32", 12)
+        got = from_dev(out, psi.shape)
+        g.close()
+        return got
+
+    monkeypatch.setenv("WL_STREAM_FIELDS", "0")
+    a = run()
+    monkeypatch.setenv("WL_STREAM_FIELDS", "1")
+    b = run()
+    assert np.array_equal(a, b)
+    ref = oracle.sign_cheb(L, U, psi, 1.5, 60, 0.003, 1.0, scale)
+    assert rel(b, ref) <= 1e-5, rel(b, ref)
