@@ -402,8 +402,9 @@ def main():
     ap.add_argument("--extras", default="cg,c2,dslash,batch,uneven,sign,overlap,clover",
                     help="side measurements outside the timed region (comma list)")
     ap.add_argument("--dslash-only", default=None,
-                    help="run only these D-slash cases (comma list of tags such as 24c48_f32_r12_12rhs, warm "
-                         "protocol) and print their results: for counter profiles of one kernel")
+                    help="run only these D-slash cases (comma list of tags such as 24c48_f32_r12_12rhs) and print "
+                         "their results: for counter profiles of one kernel")
+    ap.add_argument("--dslash-protocols", default="warm", help="with --dslash-only: warm, cold or warm,cold")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -428,7 +429,7 @@ def main():
                 gauges[lat] = w.Gauge(DSLASH_LATTICE[lat], _dev(torch, li.near_identity_links(
                     DSLASH_LATTICE[lat], 0.3, seed), dev))
         try:
-            ds = bench_dslash(w, torch, li, dev, a, gauges, only, ("warm",))
+            ds = bench_dslash(w, torch, li, dev, a, gauges, only, tuple(a.dslash_protocols.split(",")))
         finally:
             for g in gauges.values():
                 g.close()

@@ -422,13 +422,15 @@ WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
             u[(k + 1) / 3][(k + 1) % 3] = cpx<T>{(T)w.z, (T)w.w};
         }
     } else {
+        // FP16/BF16 recon-12: the first four complex entries in one 16-byte
+        // row (the first two 8-byte chunk rows of the block), the last two in
+        // the third 8-byte row: two loads per link instead of three
+        const uint4 w01 = ld_link<NT>(row_elem<uint4>(base, 0, stride, cb));
+        const uint2 w2 = ld_link<NT>(row_elem<uint2>(base, 2, stride, cb));
+        const uint32_t q[6] = {w01.x, w01.y, w01.z, w01.w, w2.x, w2.y};
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            uint2 w = ld_link<NT>(row_elem<uint2>(base, c, stride, cb));
-            const int k = 2 * c;
-            u[k / 3][k % 3] = cpx<T>{(T)lo16_to_float<P>(w.x), (T)hi16_to_float<P>(w.x)};
-            u[(k + 1) / 3][(k + 1) % 3] = cpx<T>{(T)lo16_to_float<P>(w.y), (T)hi16_to_float<P>(w.y)};
-        }
+        for (int k = 0; k < 6; ++k)
+            u[k / 3][k % 3] = cpx<T>{(T)lo16_to_float<P>(q[k]), (T)hi16_to_float<P>(q[k])};
     }
     if constexpr (R == 12) {
         // row2 = conj(row0 x row1): u2k = conj(u0i u1j - u0j u1i), (k, i, j) cyclic
@@ -471,8 +473,11 @@ WL_HD void store_link(void *base, int stride, int cb, const double u[18] /* row-
         for (int c = 0; c < 3; ++c)
             b[(size_t)c * stride + cb] = float4{(float)u[4 * c], (float)u[4 * c + 1], (float)u[4 * c + 2], (float)u[4 * c + 3]};
     } else {
-        for (int c = 0; c < 3; ++c)
-            b[(size_t)c * stride + cb] = uint2{pack2_d<P>(u[4 * c], u[4 * c + 1]), pack2_d<P>(u[4 * c + 2], u[4 * c + 3])};
+        // entries 0-3 as one 16-byte row over chunk rows 0 and 1, entries 4-5 in row 2
+        uint4 *r01 = (uint4 *)base;
+        r01[cb] = uint4{pack2_d<P>(u[0], u[1]), pack2_d<P>(u[2], u[3]), pack2_d<P>(u[4], u[5]),
+                        pack2_d<P>(u[6], u[7])};
+        b[(size_t)2 * stride + cb] = uint2{pack2_d<P>(u[8], u[9]), pack2_d<P>(u[10], u[11])};
     }
 }
 
