@@ -275,6 +275,10 @@ def dslash_sets(w, prec, recon, nrhs, vh):
     return min(n, 16), per_set
 
 
+# bytes per output site of a hop that reads every neighbour spinor from memory
+NAIVE_BYTES = {("f64", 18): 2880, ("f64", 12): 2496, ("f32", 18): 1440, ("f32", 12): 1248, ("f16", 12): 660,
+               ("bf16", 12): 660}
+
 DSLASH_CASES = [("32", "f16", 12, 1), ("32", "f32", 12, 1), ("32", "bf16", 12, 1), ("32", "f64", 18, 1),
                 ("24", "f64", 18, 1), ("24", "f64", 12, 1), ("24", "f32", 18, 1), ("24", "f32", 12, 1),
                 ("24", "f16", 12, 1), ("24b", "f32", 12, 12), ("24b", "f16", 12, 12)]
@@ -304,17 +308,27 @@ def bench_dslash(w, torch, li, dev, a, gauges, only=None, protocols=("warm", "co
         for ns, name in [(1, "warm"), (nsets, "cold")]:
             if name not in protocols:
                 continue
+            # one untimed trial (tuning, packing, warm-up launches), then the
+            # median of 5 timed trials of back-to-back launches
+            reps = 100 if nrhs == 1 else 20
             try:
-                sec = w.wl_bench_dslash(g, prec, rc, nrhs, 0, ns, 100 if nrhs == 1 else 20, stream)
+                w.wl_bench_dslash(g, prec, rc, nrhs, 0, ns, 10, stream)
+                trials = sorted(w.wl_bench_dslash(g, prec, rc, nrhs, 0, ns, reps, stream) for _ in range(5))
             except w.WilsonError as e:
                 ds["%s_%s" % (tag, name)] = {"error": str(e)}
                 continue
+            sec = trials[2]
             gbs = bps * vh / sec / 1e9
-            ds["%s_%s" % (tag, name)] = {"us": round(sec * 1e6, 2), "GBs": round(gbs, 1),
-                                         "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                         "TFLOPs": round(nrhs * 1320 * vh / sec / 1e12, 3),
-                                         "sets": ns, "rotated_MB": round(ns * per_set / 1e6, 1)}
-            log("dslash %s %s: %s" % (tag, name, ds["%s_%s" % (tag, name)]))
+            rec = {"us": round(sec * 1e6, 2), "us_min_max": [round(trials[0] * 1e6, 2), round(trials[-1] * 1e6, 2)],
+                   "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                   "TFLOPs": round(nrhs * 1320 * vh / sec / 1e12, 3),
+                   "sets": ns, "rotated_MB": round(ns * per_set / 1e6, 1)}
+            if nrhs == 1:
+                # the byte count of a hop that reads all 8 neighbours' full
+                # spinors and 18-real links (QUDA's naive model)
+                rec["naive_GBs"] = round(NAIVE_BYTES[(prec, rc)] * vh / sec / 1e9, 1)
+            ds["%s_%s" % (tag, name)] = rec
+            log("dslash %s %s: %s" % (tag, name, rec))
     return ds
 
 
@@ -379,6 +393,13 @@ def cpu_baseline(w, L, U, eta, kappa, tol, a):
     t0 = time.perf_counter()
     oracle.sign_cheb(Ls, Us, vs, 1.5, 10, 0.003, 1.0, 42.25)
     ts = time.perf_counter() - t0
+    # the small exact case (4^4 Haar links, kappa 0.12, tol 1e-12), whole solve
+    L1 = (4, 4, 4, 4)
+    U1 = li.haar_links(L1, 1001)
+    e1 = li.gaussian_spinor(L1, 2001)
+    t0 = time.perf_counter()
+    _, _, it1, _ = oracle.cg_eo(L1, U1, e1, 0.12, 1e-12)
+    r["cg_4c4_exact_case"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iters": int(it1[0])}
     r["sign_function_16c32_sample"] = {
         "sample": "1 rhs, degree 10 (21 H_W applications), %d threads" % nthreads,
         "ms": round(ts * 1e3, 1), "ms_per_hw_application": round(ts * 1e3 / 21, 2),
@@ -598,6 +619,9 @@ def main():
     copy_bytes = 256 << 20
     sec = w.wl_bench_copy(copy_bytes, 4, stream)
     out["copy_reference"] = {"bytes_each_way": copy_bytes, "GBs": round(2 * copy_bytes / sec / 1e9, 1)}
+    for rec in (out.get("dslash") or {}).values():
+        if isinstance(rec, dict) and "GBs" in rec:
+            rec["frac_of_copy"] = round(rec["GBs"] / out["copy_reference"]["GBs"], 4)
     log("copy %d MiB: %.1f GB/s (read + write)" % (copy_bytes >> 20, out["copy_reference"]["GBs"]))
 
     g.close()
