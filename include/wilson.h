@@ -48,6 +48,23 @@
  * Arguments are validated before any device work; wl_last_error() returns a
  * thread-local description of the most recent failure.  A pointer that
  * hipPointerGetAttributes does not report as device memory is WL_ERR_ARG.
+ *
+ * Environment (read at each call; none is needed for normal use):
+ *   WL_TUNE=0            no autotuning: every hop runs 256-thread blocks
+ *   WL_TUNE_FORCE=v:b[:c] pin the hop launches whose tuner candidates hold
+ *                        variant v with block size b (column height c, 4 by
+ *                        default) -- for tests of each variant
+ *   WL_GRAPHS=0          solver iteration chunks launched kernel by kernel
+ *                        instead of replayed from captured HIP graphs
+ *   WL_STREAM_FIELDS=0|1 force the solver kernels' non-temporal field access
+ *                        off or on (by default on when eight fields of the
+ *                        set exceed the 256 MB last-level cache)
+ *   WL_WAIT_TIMEOUT_S=n  seconds a solver waits for a device readback before
+ *                        it returns WL_ERR_HIP (default 600)
+ *   WL_DEBUG=1           tuner choices and a per-chunk solver trace on stderr
+ * None of them changes a result beyond floating-point rounding order:
+ * WL_GRAPHS and WL_STREAM_FIELDS give bit-identical solves; a launch
+ * configuration can change the grouping of the reductions' partial sums.
  */
 #ifndef WILSON_MI355X_H
 #define WILSON_MI355X_H
