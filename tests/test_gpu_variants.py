@@ -100,3 +100,30 @@ def test_untuned_fallback_solves(monkeypatch):
     for r in range(2):
         tr = np.linalg.norm(eta[r] - oracle.wilson(L, U, psi[r], 0.1245)) / np.linalg.norm(eta[r])
         assert st == w.WL_OK and tr <= 1e-10, (r, st, info[r], tr)
+
+
+@pytest.mark.parametrize("var,block", [(6, 256), (7, 64), (8, 256), (8, 768)])
+def test_rhs_block_variant_two_systems(var, block, force):
+    """Right-hand-side blocks across a set of two systems (3 and 5 right-hand
+    sides, different lattices and kappas): a block's waves or pairs must not
+    run into the next system's vectors, and a variant 8 block that holds all
+    right-hand sides of its system reads its links non-temporally."""
+    w = need_gpu()
+    force(var, block)
+    L1, L2 = (8, 8, 8, 8), (4, 6, 4, 8)
+    U1 = li.near_identity_links(L1, 0.3, 1006)
+    U2 = li.near_identity_links(L2, 0.3, 1007)
+    e1 = li.gaussian_spinor(L1, 2006, nrhs=3)
+    e2 = li.gaussian_spinor(L2, 2007, nrhs=5)
+    g1, g2 = w.Gauge(L1, to_dev(U1)), w.Gauge(L2, to_dev(U2))
+    x1, x2 = to_dev(np.zeros_like(e1)), to_dev(np.zeros_like(e2))
+    st, info = w.wilson_cg_multi([g1, g2], [to_dev(e1), to_dev(e2)], [x1, x2], [3, 5], [0.1245, 0.124], 1e-10,
+                                 2000, "f32", 12, 0.1)
+    p1, p2 = from_dev(x1, e1.shape), from_dev(x2, e2.shape)
+    g1.close()
+    g2.close()
+    assert st == w.WL_OK, (st, info)
+    for L, U, e, p, kappa in ((L1, U1, e1, p1, 0.1245), (L2, U2, e2, p2, 0.124)):
+        for r in range(e.shape[0]):
+            tr = np.linalg.norm(e[r] - oracle.wilson(L, U, p[r], kappa)) / np.linalg.norm(e[r])
+            assert tr <= 1e-10, (var, block, L, r, tr)
