@@ -382,9 +382,22 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
         WL_TRY(blas(S, BL_CLOV_INV, P_F64, f, 2, nullptr, no_red(), s, true, 1));
         src_o = cg.xo;
     }
-    WL_TRY(hop(S, P_F64, 18, false, 0, cg.bp, src_o, cg.epi(cg.c_bp, 1, cg.eta_e), no_red(), s));
+    // (|b'|^2 rides on that hop: it is |r|^2 for a zero initial guess)
+    WL_TRY(hop(S, P_F64, 18, false, 0, cg.bp, src_o, cg.epi(cg.c_bp, 1, cg.eta_e),
+               red_spec(S, RED_STORE, S.scal(SC_RR)), s));
     WL_TRY(pack(S, (const double *const *)x, 0, cg.xh, s));
-    WL_TRY(cg.residual64());
+    // r = b' - M x.  When every initial guess is zero (the usual start) r = b'
+    // exactly and the residual's two FP64 hops are replaced by a copy: the
+    // guesses' |x_e|^2 are read back first to decide.
+    WL_TRY(blas(S, BL_NORM2, P_F64, &cg.xh, 1, nullptr, red_spec(S, RED_STORE, S.scal(SC_TMP)), s));
+    WL_HIP(hipMemcpyAsync(hp, S.scal(SC_TMP), sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    WL_HIP(hipStreamSynchronize(s));
+    bool zero_guess = true;
+    for (int v = 0; v < nv; ++v) zero_guess = zero_guess && hp[v] == 0.0;
+    if (zero_guess)
+        WL_TRY(convert(S, cg.rh, cg.bp, s));
+    else
+        WL_TRY(cg.residual64());
     WL_HIP(hipMemcpyAsync(hp, S.sc, sizeof(double) * ExecSet::SC_N * nv, hipMemcpyDeviceToHost, s));
     WL_HIP(hipStreamSynchronize(s));
     std::vector<double> eta_n(nv), rmax(nv), last_true(nv), target(nv);
