@@ -312,6 +312,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     static_assert(SP != P_F64, "variant 8 stages FP32 links");
     __shared__ float2 s_u[8][9][64];
     __shared__ int s_n[8][64];
+    static_assert(sizeof(s_u) + sizeof(s_n) == kLdsLinkBytes, "LDS layout of variant 8");
     const int lb = xcd_remap(blockIdx.x, a.nblocks);
     const int half = a.nblocks >> 1;
     const bool second = a.twin && lb >= half;
