@@ -40,9 +40,6 @@ struct cpx {
     T re, im;
 };
 
-template <class T> WL_HD cpx<T> cmul(cpx<T> a, cpx<T> b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-// conj(a) * b
-template <class T> WL_HD cpx<T> cjmul(cpx<T> a, cpx<T> b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }
 template <class T> WL_HD cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T> WL_HD cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
 // a + i b, a - i b
@@ -52,6 +49,19 @@ template <class T> WL_HD cpx<T> csub_i(cpx<T> a, cpx<T> b) { return {a.re + b.im
 // fused multiply-add, one rounding (IEEE fma on host and device)
 WL_HD float fmadd(float a, float b, float c) { return fmaf(a, b, c); }
 WL_HD double fmadd(double a, double b, double c) { return fma(a, b, c); }
+
+// complex products with their fused multiply-adds written out: left to the
+// compiler, which of the two products gets fused can differ between kernels
+// built from the same source, and every launch variant must round alike
+template <class T> WL_HD cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {fmadd(a.re, b.re, -(a.im * b.im)), fmadd(a.re, b.im, a.im * b.re)};
+}
+// conj(a) * b
+template <class T> WL_HD cpx<T> cjmul(cpx<T> a, cpx<T> b)
+{
+    return {fmadd(a.re, b.re, a.im * b.im), fmadd(a.re, b.im, -(a.im * b.re))};
+}
 
 // ------------------------------------------------------------------ half / bf16
 
@@ -449,9 +459,10 @@ WL_HD void load_link(const void *base, int stride, int cb, cpx<T> u[3][3])
                 im = fmadd(-a.im, b.re, im);
                 return {re, im};
             } else {
-                // FP64 (memory-bound): independent products keep fewer registers live
-                return {a.re * b.re - a.im * b.im - (c.re * d.re - c.im * d.im),
-                        -(a.re * b.im + a.im * b.re - (c.re * d.im + c.im * d.re))};
+                // FP64 (memory-bound): independent products keep fewer registers
+                // live; conj(a b - c d), fused multiply-adds written out
+                const cpx<T> ab = cmul(a, b), cd = cmul(c, d);
+                return {ab.re - cd.re, cd.im - ab.im};
             }
         };
         u[2][0] = cross(u[0][1], u[1][2], u[0][2], u[1][1]);

@@ -127,3 +127,30 @@ def test_rhs_block_variant_two_systems(var, block, force):
         for r in range(e.shape[0]):
             tr = np.linalg.norm(e[r] - oracle.wilson(L, U, p[r], kappa)) / np.linalg.norm(e[r])
             assert tr <= 1e-10, (var, block, L, r, tr)
+
+
+@pytest.mark.parametrize("prec,recon", [("f32", 12), ("f16", 12), ("bf16", 12), ("f32", 18), ("f64", 18)])
+def test_variants_and_batching_agree_bitwise(prec, recon, monkeypatch):
+    """Every launch variant runs the same per-site arithmetic in the same
+    order, so they agree bit for bit: one right-hand side per thread, several
+    per block (waves or pairs), links staged in LDS, every fence width and
+    link-cache hint; and a 5-RHS D-slash equals five 1-RHS ones."""
+    w = need_gpu()
+    L = (8, 6, 4, 8)
+    U = li.haar_links(L, 43)
+    psi = li.gaussian_spinor(L, 44, nrhs=5)
+    cfgs = ["0:256", "1:128", "2:512", "3:64", "3:1024:16", "6:256", "7:64", "8:256", "8:768"]
+    if prec in ("f16", "bf16"):
+        cfgs += ["4:256", "5:512"]
+    for parity, dagger in [(0, 0), (1, 1), (-1, 0)]:
+        ref = None
+        for c in cfgs:
+            monkeypatch.setenv("WL_TUNE_FORCE", c)
+            got = run_dslash(w, L, U, psi, 0.13, parity, dagger, prec, recon)
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), (prec, recon, parity, dagger, c)
+        monkeypatch.delenv("WL_TUNE_FORCE")
+        for r in range(psi.shape[0]):
+            one = run_dslash(w, L, U, psi[r:r + 1], 0.13, parity, dagger, prec, recon)
+            assert np.array_equal(one[0], ref[r]), (prec, recon, parity, dagger, r)
