@@ -608,8 +608,11 @@ WL_HD void clover_apply(const void *base, int stride, int cb, T o[24])
                 // M_ij = (re, im) for i < j; M_ij = conj(M_ji) for i > j
                 const int u = i < j ? clov_upper(i, j) : clov_upper(j, i);
                 const T mr = m[u], mi = i < j ? m[u + 1] : -m[u + 1];
-                yr += mr * xr[j] - mi * xi[j];
-                yi += mr * xi[j] + mi * xr[j];
+                // fused multiply-adds written out (every launch variant rounds alike)
+                yr = fmadd(mr, xr[j], yr);
+                yr = fmadd(-mi, xi[j], yr);
+                yi = fmadd(mr, xi[j], yi);
+                yi = fmadd(mi, xr[j], yi);
             }
             o[12 * b + 2 * i] = yr;
             o[12 * b + 2 * i + 1] = yi;

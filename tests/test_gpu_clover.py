@@ -139,3 +139,25 @@ def test_clover_validation(links):
         w.wilson_clover_dslash(g, to_dev(eta), x, 1, KAPPA, CSW, 0, "f16", 18)
     assert e.value.status == w.WL_ERR_PREC
     g.close()
+
+
+@pytest.mark.parametrize("prec,recon", [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)])
+def test_clover_variants_agree_bitwise(links, prec, recon, monkeypatch):
+    """The clover epilogue writes out its fused multiply-adds, so every launch
+    variant that runs it (fence 2 with non-temporal or cached links; for half
+    precision also fence 4) gives the same operator bit for bit."""
+    w = need_gpu()
+    psi = li.gaussian_spinor(L, 2302, nrhs=2)
+    cfgs = ["0:256", "0:64", "3:512", "3:1024:16"] + (["4:256", "5:128"] if prec in ("f16", "bf16") else [])
+    for dagger in (0, 1):
+        ref = None
+        for c in cfgs:
+            monkeypatch.setenv("WL_TUNE_FORCE", c)
+            g = w.Gauge(L, to_dev(links))
+            out = to_dev(np.zeros_like(psi))
+            w.wilson_clover_dslash(g, to_dev(psi), out, 2, KAPPA, CSW, dagger, prec, recon)
+            got = from_dev(out, psi.shape)
+            g.close()
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), (prec, recon, dagger, c)
