@@ -332,6 +332,26 @@ def bench_dslash(w, torch, li, dev, a, gauges, only=None, protocols=("warm", "co
     return ds
 
 
+def copy_reference(w, stream, ds):
+    """Bandwidth reference: a plain non-temporal copy of a known size (read +
+    write); its rocprofv3 FETCH_SIZE / WRITE_SIZE readings calibrate the
+    traffic counters.  Beside it, what ordinary (cached) accesses reach when
+    the operands fit the 256 MB last-level cache (a 64 MiB copy, a 128 MiB
+    read) and when they do not (a 1 GiB read).  Adds each D-slash record's
+    fraction of the copy rate."""
+    copy_bytes = 256 << 20
+    sec = w.wl_bench_copy(copy_bytes, 4, stream)
+    ref = {"bytes_each_way": copy_bytes, "GBs": round(2 * copy_bytes / sec / 1e9, 1)}
+    for key, nbytes, mode, moved in (("cached_copy_64MiB_GBs", 64 << 20, 1, 2), ("cached_read_128MiB_GBs", 128 << 20, 2, 1),
+                                     ("read_1GiB_GBs", 1 << 30, 2, 1)):
+        ref[key] = round(moved * nbytes / w.wl_bench_copy(nbytes, 50 if nbytes < (1 << 30) else 10, stream, mode) / 1e9, 1)
+    for rec in (ds or {}).values():
+        if isinstance(rec, dict) and "GBs" in rec:
+            rec["frac_of_copy"] = round(rec["GBs"] / ref["GBs"], 4)
+    log("copy %d MiB: %.1f GB/s (read + write)" % (copy_bytes >> 20, ref["GBs"]))
+    return ref
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -454,7 +474,8 @@ def main():
         finally:
             for g in gauges.values():
                 g.close()
-        print(json.dumps({"dslash": ds}), flush=True)
+        out = {"dslash": ds, "copy_reference": copy_reference(w, torch.cuda.current_stream(), ds)}
+        print(json.dumps(out), flush=True)
         return 0
     L = (32, 32, 32, 64)
     vh = int(np.prod(L)) // 2
@@ -614,15 +635,7 @@ def main():
     if side:
         out["configs"] = side
 
-    # bandwidth reference: a plain copy of a known size (read + write); its
-    # rocprofv3 FETCH_SIZE / WRITE_SIZE readings calibrate the traffic counters
-    copy_bytes = 256 << 20
-    sec = w.wl_bench_copy(copy_bytes, 4, stream)
-    out["copy_reference"] = {"bytes_each_way": copy_bytes, "GBs": round(2 * copy_bytes / sec / 1e9, 1)}
-    for rec in (out.get("dslash") or {}).values():
-        if isinstance(rec, dict) and "GBs" in rec:
-            rec["frac_of_copy"] = round(rec["GBs"] / out["copy_reference"]["GBs"], 4)
-    log("copy %d MiB: %.1f GB/s (read + write)" % (copy_bytes >> 20, out["copy_reference"]["GBs"]))
+    out["copy_reference"] = copy_reference(w, stream, out.get("dslash"))
 
     g.close()
     if not a.no_cpu:

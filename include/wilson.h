@@ -316,8 +316,14 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
                           int32_t nsets, int32_t reps, double *seconds_per_call, void *stream);
 
 /* Time a plain device copy of `bytes` bytes (read + write), the measured
- * bandwidth reference for the roofline; mean seconds per copy. */
-wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, void *stream);
+ * bandwidth reference for the roofline; mean seconds per launch of `reps`
+ * back-to-back launches (after one untimed launch) on library-owned buffers.
+ * mode 0: non-temporal loads and stores (the roofline reference and the
+ * traffic-counter calibration); 1: ordinary loads and stores, so that
+ * operands that fit the last-level cache are served from it; 2: ordinary
+ * loads only (`bytes` read per launch, nothing written).  WL_ERR_ARG for
+ * bytes < 1024, reps < 1 or another mode. */
+wl_status wl_bench_copy(int64_t bytes, int32_t reps, int32_t mode, double *seconds_per_call, void *stream);
 
 /* Per-kernel timing of the library's own hop launches: when enabled, every
  * hop launch outside graph capture drains its stream and is dispatched with

@@ -93,6 +93,30 @@ __global__ __launch_bounds__(256) void k_copy_bw(const float4 *__restrict__ in, 
     if (i < n) WL_NT_STORE(nt_f4, WL_NT_LOAD(nt_f4, in + i), out + i);
 }
 
+// The same copy with ordinary (cached) loads and stores: operands small enough
+// for the last-level cache stay there between launches.
+__global__ __launch_bounds__(256) void k_copy_cached(const float4 *__restrict__ in, float4 *__restrict__ out, size_t n)
+{
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+// Read-only reference: each thread sums four 16-byte elements a grid apart
+// with ordinary loads; the sum is stored only when it equals a value a zeroed
+// buffer never produces, so no store reaches memory.
+__global__ __launch_bounds__(256) void k_read_cached(const float4 *__restrict__ in, float *__restrict__ out, size_t n)
+{
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x, st = (size_t)gridDim.x * blockDim.x;
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i + k * st < n) {
+            const float4 v = in[i + k * st];
+            s += (v.x + v.y) + (v.z + v.w);
+        }
+    if (s == 1.0f) out[blockIdx.x] = s;
+}
+
 template <int P>
 static hipError_t launch_pack_t(bool unpack, const PackArgs &a, int block, hipStream_t s)
 {
@@ -143,13 +167,22 @@ hipError_t launch_pack_gauge(int prec, int recon, const double *U, void *out, co
     return hipGetLastError();
 }
 
-hipError_t launch_copy_bw(const void *in, void *out, size_t bytes, hipStream_t s)
+hipError_t launch_copy_bw(int mode, const void *in, void *out, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / sizeof(float4);
     const int blk = 256;
-    const size_t grid = (n + blk - 1) / blk;
-    if (grid > 0x7FFFFFFFu) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_copy_bw, dim3((unsigned)grid), dim3(blk), 0, s, (const float4 *)in, (float4 *)out, n);
+    // the read-only kernel takes four elements per thread and stores at most
+    // one float per block into `out` (which holds `bytes` bytes)
+    const size_t grid = mode == 2 ? (n / 4 + blk - 1) / blk : (n + blk - 1) / blk;
+    if (grid > 0x7FFFFFFFu || grid == 0) return hipErrorInvalidValue;
+    if (mode == 0)
+        hipLaunchKernelGGL(k_copy_bw, dim3((unsigned)grid), dim3(blk), 0, s, (const float4 *)in, (float4 *)out, n);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_copy_cached, dim3((unsigned)grid), dim3(blk), 0, s, (const float4 *)in, (float4 *)out, n);
+    else if (mode == 2)
+        hipLaunchKernelGGL(k_read_cached, dim3((unsigned)grid), dim3(blk), 0, s, (const float4 *)in, (float *)out, n);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

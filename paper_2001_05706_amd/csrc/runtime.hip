@@ -1308,10 +1308,11 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
     return st;
 }
 
-wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, void *stream)
+wl_status wl_bench_copy(int64_t bytes, int32_t reps, int32_t mode, double *seconds_per_call, void *stream)
 {
     clear_error();
     if (bytes < 1024 || reps < 1 || !seconds_per_call) return set_error(WL_ERR_ARG, "bytes >= 1024, reps >= 1");
+    if (mode < 0 || mode > 2) return set_error(WL_ERR_ARG, "copy mode %d is not 0, 1 or 2", mode);
     bytes &= ~(int64_t)15;
     hipStream_t s = (hipStream_t)stream;
     void *a = nullptr, *b = nullptr;
@@ -1325,10 +1326,12 @@ wl_status wl_bench_copy(int64_t bytes, int32_t reps, double *seconds_per_call, v
     if (hipMemsetAsync(a, 0, bytes, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
         hipEventCreate(&e1) != hipSuccess)
         st = set_error(WL_ERR_HIP, "setup failed");
-    if (st == WL_OK && launch_copy_bw(a, b, bytes, s) != hipSuccess) st = set_error(WL_ERR_HIP, "copy launch failed");
+    // (the read-only mode reads a every time; b receives no store from a zeroed a)
+    if (st == WL_OK && hipMemsetAsync(b, 0, bytes, s) != hipSuccess) st = set_error(WL_ERR_HIP, "setup failed");
+    if (st == WL_OK && launch_copy_bw(mode, a, b, bytes, s) != hipSuccess) st = set_error(WL_ERR_HIP, "copy launch failed");
     if (st == WL_OK) (void)hipEventRecord(e0, s);
     for (int r = 0; r < reps && st == WL_OK; ++r)
-        if (launch_copy_bw((r & 1) ? b : a, (r & 1) ? a : b, bytes, s) != hipSuccess)
+        if (launch_copy_bw(mode, (r & 1) && mode != 2 ? b : a, (r & 1) && mode != 2 ? a : b, bytes, s) != hipSuccess)
             st = set_error(WL_ERR_HIP, "copy launch failed");
     float ms = 0.f;
     if (st == WL_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

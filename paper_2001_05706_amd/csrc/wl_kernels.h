@@ -91,6 +91,7 @@ hipError_t launch_clover_build(const double *U_canon, const SysDesc &d, double k
                                hipStream_t s);
 hipError_t launch_clover_invert(const SysDesc &d, const void *A64, void *Ainv64, void *Ainv32, void *Ainv16,
                                 hipStream_t s);
-hipError_t launch_copy_bw(const void *in, void *out, size_t bytes, hipStream_t s);
+// mode 0: non-temporal copy; 1: cached copy; 2: cached read-only sum
+hipError_t launch_copy_bw(int mode, const void *in, void *out, size_t bytes, hipStream_t s);
 
 }  // namespace wl

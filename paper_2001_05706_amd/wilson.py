@@ -79,7 +79,7 @@ SIGNATURES = [
     ("wl_status_string", ctypes.c_char_p, [_i32]),
     ("wl_last_error", ctypes.c_char_p, []),
     ("wl_bench_dslash", _i32, [_P, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_d), _P]),
-    ("wl_bench_copy", _i32, [_i64, _i32, ctypes.POINTER(_d), _P]),
+    ("wl_bench_copy", _i32, [_i64, _i32, _i32, ctypes.POINTER(_d), _P]),
     ("wl_prof_enable", _i32, [_i32]),
     ("wl_prof_select", _i32, [_i32]),
     ("wl_prof_read", _i32, [ctypes.POINTER(_i64), ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
@@ -314,9 +314,10 @@ def wl_bench_dslash(U: Gauge, prec="f32", recon=12, nrhs=1, parity=0, nsets=1, r
     return r.value
 
 
-def wl_bench_copy(nbytes, reps=20, stream=None) -> float:
+def wl_bench_copy(nbytes, reps=20, stream=None, mode=0) -> float:
+    """mode 0: non-temporal copy, 1: cached copy, 2: cached read-only."""
     r = ctypes.c_double()
-    _check(lib().wl_bench_copy(int(nbytes), int(reps), ctypes.byref(r), _stream(stream)))
+    _check(lib().wl_bench_copy(int(nbytes), int(reps), int(mode), ctypes.byref(r), _stream(stream)))
     return r.value
 
 

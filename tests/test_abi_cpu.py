@@ -76,4 +76,6 @@ def test_validation_before_device_work(w):
     assert lib.wilson_clover_dslash(None, None, None, 1, 0.12, 1.0, 0, 1, 12, None) == w.WL_ERR_ARG
     ev = (ctypes.c_double * 1)()
     assert lib.wl_hw_eigs(None, 1.5, 1, 2, 8, 1e-8, 10, 1.0, None, ev, ev, None, None) == w.WL_ERR_ARG
-    assert lib.wl_bench_copy(10, 1, None, None) == w.WL_ERR_ARG
+    assert lib.wl_bench_copy(10, 1, 0, None, None) == w.WL_ERR_ARG
+    sec = ctypes.c_double()
+    assert lib.wl_bench_copy(1 << 20, 1, 3, ctypes.byref(sec), None) == w.WL_ERR_ARG
