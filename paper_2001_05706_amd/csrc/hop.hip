@@ -39,22 +39,31 @@ namespace wl {
 //      before any wave starts its hop: no right-hand side repeats a link load,
 //      the recon-12 arithmetic or the site-coordinate arithmetic (FP32 and
 //      half-precision storage; not with the clover epilogue)
+//   9: pencil blocks (k_hop_pencil): the waves of a block take the same 64
+//      positions of consecutive time slices and pass each other their time
+//      neighbours through LDS; fence 2, non-temporal links
+//  10: pencil blocks with cached links; fence 4 for FP16/BF16, 2 for FP32
+//      (FP32 and half-precision storage, Wilson epilogue; lattices whose time
+//      slices hold a multiple of 64 sites)
 // Variants 4 and 5 exist for FP16/BF16 storage only (FP32 and FP64 operands of
 // four directions do not fit the registers); for those they repeat variant 3.
 template <int SP, int VAR> struct HopVar {
     static constexpr bool half = SP == P_F16 || SP == P_BF16;
-    static constexpr int fence = VAR == 0 || VAR == 3 || VAR == 6 ? 2 : (VAR == 4 || VAR == 5 ? (half ? 4 : 2) : 1);
+    static constexpr int fence = VAR == 0 || VAR == 3 || VAR == 6 || VAR == 9
+                                     ? 2
+                                     : (VAR == 4 || VAR == 5 || VAR == 10 ? (half ? 4 : 2) : 1);
     static constexpr int waves = SP == P_F64 ? (VAR == 0 || VAR >= 3 ? 2 : 3)
-                                             : (VAR == 7 ? 3 : VAR == 0 || VAR == 3 || VAR == 4 || VAR == 6 ? 4
-                                                                 : VAR == 2 ? 6 : 5);
-    static constexpr bool nt = VAR < 3;
+                                             : (VAR == 7 ? 3 : VAR == 0 || VAR == 3 || VAR == 4 || VAR == 6 || VAR >= 9
+                                                                   ? 4
+                                                                   : VAR == 2 ? 6 : 5);
+    static constexpr bool nt = VAR < 3 || VAR == 9;
     static constexpr bool rhs_waves = VAR == 6;
     static constexpr bool rhs_pairs = VAR == 7;
     // largest block: 1024 threads (16 waves on one CU, 4 per SIMD) where the
     // occupancy target already allows 4 waves per SIMD; 512 otherwise
     static constexpr int max_block = waves >= 4 && VAR < 6 ? 1024 : 512;
 };
-constexpr int kHopVariants = 9;
+constexpr int kHopVariants = 11;
 
 // The fields of the output parity a block computes: the launch's first slot,
 // or for the second half of a twin launch the second one.  X and Xn point into
@@ -388,16 +397,148 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     }
 }
 
+// Variants 9 and 10: pencil blocks.  The nw = block / 64 waves of a block
+// take the same 64 positions of nw consecutive time slices of one vector
+// (wave j: slice t0 + j; the set's slices hold a multiple of 64 sites and nw
+// divides the time extent).  In the checkerboard index the time neighbours of
+// output site cb are the input sites cb +- (sites per slice), at the same
+// position: the input row at wave j's own sites is the forward time
+// neighbour of wave j - 1 and the backward one of wave j + 1.  Each wave puts
+// that row into LDS once; inside the block the time directions read it there,
+// and only the outer slices fetch a time row from memory.  (The stand-alone
+// hop fetches every input spinor about twice, and the second fetch is the
+// time rows'.)  LDS holds per wave the row's raw chunks, [chunk][lane], and
+// for FP16/BF16 its norms.  Every direction runs the per-site arithmetic of
+// hop_site in its order, so the result equals the other variants' bit for bit.
+template <int SP> struct PencilRow {
+    using CH = typename SpinorFmt<SP>::chunk;
+    static constexpr int NC = SpinorFmt<SP>::nchunk;
+    static constexpr bool HALF = SP == P_F16 || SP == P_BF16;
+    static constexpr int chunk_bytes = NC * 64 * (int)sizeof(CH);
+    static constexpr int bytes = chunk_bytes + (HALF ? 64 * (int)sizeof(float) : 0);
+};
+
+// the time direction DIR of output site cb from the neighbour row in LDS
+// (interior slices of the block: no wrap, no boundary sign)
+template <int SP, int GP, int R, int DIR, bool DAG, bool NT>
+__device__ __forceinline__ void pencil_t(const HopSite &hs, int parity, int cb, int ncb, const unsigned char *row,
+                                         int lane, float acc[24])
+{
+    using P = PencilRow<SP>;
+    constexpr int SG = (DIR > 0) == DAG ? +1 : -1;
+    const typename P::CH *src = reinterpret_cast<const typename P::CH *>(row);
+    cpx<float> h0[3], h1[3];
+    float f;
+    if constexpr (P::HALF) {
+        uint32_t q[12];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint4 w = src[c * 64 + lane];
+            q[4 * c] = w.x;
+            q[4 * c + 1] = w.y;
+            q[4 * c + 2] = w.z;
+            q[4 * c + 3] = w.w;
+        }
+        const float nrm = reinterpret_cast<const float *>(row + P::chunk_bytes)[lane];
+        project_half<SP, 3, SG>(q, h0, h1);
+        f = nrm * hs.scale;
+    } else {
+        float v[24];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const float4 w = src[c * 64 + lane];
+            v[4 * c] = w.x;
+            v[4 * c + 1] = w.y;
+            v[4 * c + 2] = w.z;
+            v[4 * c + 3] = w.w;
+        }
+        project<3, SG>(v, h0, h1);
+        f = 1.f;
+    }
+    cpx<float> u[3][3];
+    hop_link<GP, R, 3, DIR, NT>(hs, parity, cb, ncb, u);
+    hop_accumulate<SP, 3, DIR, SG>(u, h0, h1, f, acc);
+}
+
+template <int SP, int GP, int R, bool DAG, int VAR>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HopVar<SP, VAR>::waves)))
+void k_hop_pencil(HopArgs a)
+{
+    static_assert(SP != P_F64, "pencil rows hold FP32 or half-precision spinors");
+    using P = PencilRow<SP>;
+    using CH = typename P::CH;
+    constexpr int FENCE = HopVar<SP, VAR>::fence;
+    constexpr bool NT = HopVar<SP, VAR>::nt;
+    extern __shared__ uint4 s_pencil[];
+    unsigned char *rows = reinterpret_cast<unsigned char *>(s_pencil);
+
+    const int lb = xcd_remap(blockIdx.x, a.nblocks);
+    const BlkMap bm = a.map[lb];
+    if (a.active && !a.active[a.one ? 0 : bm.v]) return;  // uniform over the block
+    const VecDesc vd = a.vec[a.one ? 0 : bm.v];
+    const SysDesc sd = a.sys[a.one ? 0 : vd.sys];
+    if (a.stamps && threadIdx.x == 0) a.stamps[2 * lb] = (unsigned long long)wall_clock64();
+    const HopIO f{a.parity, a.in, a.in_norm, a.out, a.out_norm, a.epi.X, a.epi.Xn};
+    const int lane = (int)threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int nw = (int)blockDim.x >> 6;
+    const int slice = sd.Lxh * sd.L[1] * sd.L[2], nch = slice >> 6;
+    const int pz = bm.lblk / nch;
+    const int cb = (pz * nw + w) * slice + (bm.lblk - pz * nch) * 64 + lane;
+    const HopSite hs = hop_input<SP>(a, f, vd, sd);
+
+    // this wave's row: the input site at the thread's own index
+    unsigned char *own = rows + w * P::bytes;
+#pragma unroll
+    for (int c = 0; c < P::NC; ++c)
+        reinterpret_cast<CH *>(own)[c * 64 + lane] = ld_field<false>(row_elem<CH>(hs.in, c, hs.stride, cb));
+    if constexpr (P::HALF)
+        reinterpret_cast<float *>(own + P::chunk_bytes)[lane] = ld_field<false>(row_elem<float>(hs.in_norm, 0, 0, cb));
+
+    float acc[24];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = 0.f;
+    const Site st = cb_coords(sd, cb, f.parity);
+    hop_dir<SP, GP, R, 0, +1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    hop_dir<SP, GP, R, 0, -1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    if constexpr (FENCE <= 2) sched_fence(acc);
+    hop_dir<SP, GP, R, 1, +1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    hop_dir<SP, GP, R, 1, -1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    sched_fence(acc);
+    __syncthreads();  // every wave's row is in LDS
+    hop_dir<SP, GP, R, 2, +1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    hop_dir<SP, GP, R, 2, -1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    if constexpr (FENCE <= 2) sched_fence(acc);
+    if (w + 1 < nw)
+        pencil_t<SP, GP, R, +1, DAG, NT>(hs, f.parity, cb, cb + slice, rows + (w + 1) * P::bytes, lane, acc);
+    else
+        hop_dir<SP, GP, R, 3, +1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    if (w > 0)
+        pencil_t<SP, GP, R, -1, DAG, NT>(hs, f.parity, cb, cb - slice, rows + (w - 1) * P::bytes, lane, acc);
+    else
+        hop_dir<SP, GP, R, 3, -1, DAG, NT>(sd, hs, f.parity, st, cb, acc);
+    sched_fence(acc);
+
+    double rv[3] = {0.0, 0.0, 0.0};
+    hop_epilogue<SP, false>(a, f, vd, sd, cb, acc, rv);
+    if (a.red.kind != RED_NONE) block_reduce_store_n(a.red, vd.pslot0, bm.lblk, rv);
+    if (a.stamps) {
+        __syncthreads();
+        if (threadIdx.x == 0) a.stamps[2 * lb + 1] = (unsigned long long)wall_clock64();
+    }
+}
+
 // With events, the dispatch itself records them at the kernel's start and end
 // (the kernel-timing form of the launch), so the measured interval is the
 // kernel alone.
 template <class K>
-static void dispatch(K kernel, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+static void dispatch(K kernel, const HopArgs &a, int block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                     unsigned lds = 0)
 {
     if (e0)
-        hipExtLaunchKernelGGL(kernel, dim3(a.nblocks), dim3(block), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(kernel, dim3(a.nblocks), dim3(block), lds, s, e0, e1, 0, a);
     else
-        hipLaunchKernelGGL(kernel, dim3(a.nblocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL(kernel, dim3(a.nblocks), dim3(block), lds, s, a);
 }
 
 template <int SP, int GP, int R, int VAR>
@@ -439,11 +580,27 @@ static hipError_t launch_hop_t(int var, bool dag, bool clov, const HopArgs &a, i
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
+    case 9:
+    case 10:
+        if constexpr (SP != P_F64) {
+            // 2 to 8 slices per block, one vector per block, no twin launch
+            if (clov || a.twin || block % 64 != 0 || block < 128 || block > 512) return hipErrorInvalidValue;
+            const unsigned lds = (unsigned)(block / 64 * PencilRow<SP>::bytes);
+            if (var == 9)
+                dispatch(dag ? k_hop_pencil<SP, GP, R, true, 9> : k_hop_pencil<SP, GP, R, false, 9>, a, block, s, e0,
+                         e1, lds);
+            else
+                dispatch(dag ? k_hop_pencil<SP, GP, R, true, 10> : k_hop_pencil<SP, GP, R, false, 10>, a, block, s,
+                         e0, e1, lds);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
 
-int hop_variants(int prec) { return prec == P_F64 ? kHopVariants - 1 : kHopVariants; }  // no variant 8 in FP64
+// FP64 runs variants 0-7 (variants 8-10 stage FP32 or half-precision data in LDS)
+int hop_variants(int prec) { return prec == P_F64 ? 8 : kHopVariants; }
 
 hipError_t launch_hop(int prec, int recon, bool dag, bool clov, int var, const HopArgs &a, int block, hipStream_t s,
                       hipEvent_t e0, hipEvent_t e1)

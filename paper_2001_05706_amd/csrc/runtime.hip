@@ -444,9 +444,21 @@ wl_status ExecSet::layout(int B, const Layout **out, int col)
     Layout L;
     L.B = B;
     // B < 0: blocks of -B right-hand sides (one wave each) on 64 sites;
-    // B >= kPairLayout: blocks of B - kPairLayout sites of two right-hand sides
-    const bool pairs = B >= kPairLayout;
-    const int G = B < 0 ? -B : (pairs ? 2 : 1), sites = B < 0 ? 64 : (pairs ? B - kPairLayout : B);
+    // B >= kPairLayout: blocks of B - kPairLayout sites of two right-hand sides;
+    // B >= kPencilLayout: blocks of 64 positions x B - kPencilLayout time slices
+    const bool pencil = B >= kPencilLayout, pairs = !pencil && B >= kPairLayout;
+    const int T = pencil ? B - kPencilLayout : 1;
+    const int G = B < 0 ? -B : (pairs ? 2 : 1),
+              sites = B < 0 ? 64 : (pencil ? 64 * T : (pairs ? B - kPairLayout : B));
+    if (pencil) {
+        if (T < 1) return set_error(WL_ERR_ARG, "pencil blocks of %d time slices", T);
+        for (auto &e : systems) {
+            const SysDesc &g = e.g->geom;
+            if ((g.Lxh * g.L[1] * g.L[2]) % 64 != 0 || g.L[3] % T != 0)
+                return set_error(WL_ERR_ARG, "pencil blocks of %d slices do not tile a %dx%dx%dx%d lattice", T,
+                                 g.L[0], g.L[1], g.L[2], g.L[3]);
+        }
+    }
     std::vector<VecDesc> hv = vec;
     std::vector<BlkMap> map;
     int ps = 0, vbase = 0;
@@ -465,11 +477,15 @@ wl_status ExecSet::layout(int B, const Layout **out, int col)
         // planes away in launch order rather than a whole slice: the spinors a
         // wave's neighbours need are still in the XCD's L2 when they are read.
         // (The tuner chooses the column height with the launch variant.)
+        // (a pencil block b covers slices t0 .. t0 + T - 1 at the 64 positions
+        // of chunk b % (slice / 64), t0 = T (b / (slice / 64)), and is ordered by
+        // its first slice)
         const SysDesc &g = systems[i].g->geom;
         const int plane = g.Lxh * g.L[1], slice = plane * g.L[2], tg = (g.L[3] + 7) / 8;
         std::vector<std::array<int, 5>> key(nb);
         for (int b = 0; b < nb; ++b) {
-            const int cb0 = b * sites, t = cb0 / slice, z = (cb0 % slice) / plane;
+            const int cb0 = pencil ? (b / (slice / 64)) * T * slice + (b % (slice / 64)) * 64 : b * sites;
+            const int t = cb0 / slice, z = (cb0 % slice) / plane;
             key[b] = {t / tg, z / col, t, z, b};
         }
         std::sort(key.begin(), key.end());
@@ -685,6 +701,11 @@ std::vector<int> hop_candidates(int prec)
             // two FP64 accumulators fit only at 2 waves per SIMD, where variant 7 measured
             // slower than 3 and 6 (12-RHS recon-12 D-slash: 700 us against 672 us)
             if (v == 7 && prec == P_F64) continue;
+            // pencil blocks of 2, 4 or 8 time slices
+            if (v == 9 || v == 10) {
+                for (int b : {128, 256, 512}) c.push_back(cfg_make(v, b, col));
+                continue;
+            }
             for (int b : {64, 128, 256, 512}) c.push_back(cfg_make(v, b, col));
             // 1024-thread blocks where the variant runs 4 or more waves per SIMD
             // (FP32 and half-precision storage, variants 0-5; see HopVar::max_block)
@@ -699,7 +720,41 @@ std::vector<int> hop_candidates(int prec)
 static wl_status hop_layout(ExecSet &S, int cfg, const Layout **L)
 {
     const int var = cfg_var(cfg), B = cfg_block(cfg);
-    return S.layout(var == 6 || var == 8 ? -(B / 64) : var == 7 ? kPairLayout + B : B, L, cfg_col(cfg));
+    const int key = var == 6 || var == 8 ? -(B / 64)
+                    : var == 7           ? kPairLayout + B
+                    : var >= 9           ? kPencilLayout + B / 64
+                                         : B;
+    return S.layout(key, L, cfg_col(cfg));
+}
+
+// The candidates of a hop launch on this set: variants 6-8 need several
+// right-hand sides in a system, the clover epilogue the registers of the
+// two-direction variants (0 and 3) without LDS staging, and pencil blocks
+// (9, 10) time slices of a multiple of 64 sites and a time extent that their
+// slice count divides.
+static std::vector<int> hop_cands(const ExecSet &S, int prec, bool clov)
+{
+    int max_nrhs = 0;
+    bool slices64 = true;
+    for (auto &e : S.systems) {
+        max_nrhs = std::max(max_nrhs, e.nrhs);
+        const SysDesc &g = e.g->geom;
+        slices64 = slices64 && (g.Lxh * g.L[1] * g.L[2]) % 64 == 0;
+    }
+    std::vector<int> cands;
+    for (int c : hop_candidates(prec)) {
+        const int v = cfg_var(c);
+        if (clov && (v == 1 || v == 2 || v >= 8)) continue;
+        if (max_nrhs < 2 && v >= 6 && v <= 8) continue;
+        if (v >= 9) {
+            bool ok = slices64;
+            for (auto &e : S.systems) ok = ok && e.g->geom.L[3] % (cfg_block(c) / 64) == 0;
+            if (!ok) continue;
+        }
+        cands.push_back(c);
+    }
+    if (cands.empty()) cands.push_back(cfg_make(0, 256, 4));
+    return cands;
 }
 
 wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &out, const Field &in, const Epi &e,
@@ -738,16 +793,7 @@ wl_status hop(ExecSet &S, int prec, int recon, bool dag, int par, const Field &o
     // prefer another variant than a plain one
     const std::string key = hop_key(S, prec, recon, dag) + (clov ? "/clov" : "") + "/x" + std::to_string(e.nx) +
                             (red.kind != RED_NONE ? "/r" : "");
-    std::vector<int> cands = hop_candidates(prec);
-    if (clov)  // the clover epilogue needs the registers of the two-direction variants (0 and 3)
-        cands.erase(std::remove_if(cands.begin(), cands.end(),
-                                   [](int c) { return cfg_var(c) == 1 || cfg_var(c) == 2 || cfg_var(c) == 8; }),
-                    cands.end());
-    int max_nrhs = 0;
-    for (auto &e : S.systems) max_nrhs = std::max(max_nrhs, e.nrhs);
-    if (max_nrhs < 2)  // right-hand-side blocks and pairs need several right-hand sides
-        cands.erase(std::remove_if(cands.begin(), cands.end(), [](int c) { return cfg_var(c) >= 6; }), cands.end());
-    if (cands.empty()) cands = hop_candidates(prec);
+    const std::vector<int> cands = hop_cands(S, prec, clov);
     const int cfg = tuned_block(key, cands, s, [&](int c) -> hipError_t {
         const Layout *L = nullptr;
         if (hop_layout(S, c, &L) != WL_OK) return hipErrorOutOfMemory;
@@ -1259,7 +1305,7 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
         Epi e;
         e.coef = coef;
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
-        cfg = tuned_block(hop_key(*S, prec, recon, false) + "/x0", hop_candidates(prec), s,
+        cfg = tuned_block(hop_key(*S, prec, recon, false) + "/x0", hop_cands(*S, prec, false), s,
                           [](int) { return hipSuccess; });
         B = cfg_block(cfg);
         if (st == WL_OK) st = hop_layout(*S, cfg, &L);

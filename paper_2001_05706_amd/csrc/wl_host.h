@@ -111,8 +111,10 @@ struct SysEntry {
     double csw = 0.0;  // clover coefficient; 0: Wilson operator
 };
 
-// ExecSet::layout keys at and above this value denote pair layouts
+// ExecSet::layout keys at and above kPairLayout denote pair layouts, at and
+// above kPencilLayout pencil layouts
 constexpr int kPairLayout = 1 << 16;
+constexpr int kPencilLayout = 1 << 17;
 
 // A set of systems (each a gauge handle with nrhs right-hand sides) whose
 // vectors share every field and every launch.
@@ -144,7 +146,11 @@ public:
     // device tables: prec < 0 geometry only; recon 0: no links (geometry and clover term)
     wl_status sys_table(int prec, int recon, hipStream_t s, const SysDesc **out);
     // B > 0: blocks of B sites of one vector; B < 0: blocks of -B vectors on 64
-    // sites; B >= kPairLayout: blocks of B - kPairLayout sites of two vectors
+    // sites; B >= kPairLayout: blocks of B - kPairLayout sites of two vectors;
+    // B >= kPencilLayout: blocks of one vector on the same 64 positions of
+    // B - kPencilLayout consecutive time slices (every system's slices must
+    // hold a multiple of 64 sites and its time extent be a multiple of the
+    // slice count; WL_ERR_ARG otherwise)
     // col: z-planes per column of the block order (see the definition)
     wl_status layout(int B, const Layout **out, int col = 4);
     int32_t *d_active = nullptr;

@@ -154,3 +154,89 @@ def test_variants_and_batching_agree_bitwise(prec, recon, monkeypatch):
         for r in range(psi.shape[0]):
             one = run_dslash(w, L, U, psi[r:r + 1], 0.13, parity, dagger, prec, recon)
             assert np.array_equal(one[0], ref[r]), (prec, recon, parity, dagger, r)
+
+
+# Pencil blocks (variants 9 and 10) need time slices of a multiple of 64 sites
+# and a time extent their slice count divides: 8x8x4x8 has 128 sites per slice
+# (2 chunks of 64) and 8 slices, so blocks of 2, 4 and 8 slices all tile it.
+PENCIL_L = (8, 8, 4, 8)
+
+
+@pytest.mark.parametrize("var,block", [(9, 128), (9, 256), (9, 512), (10, 128), (10, 256), (10, 512)])
+def test_pencil_variant_matches_oracle(var, block, force):
+    """(FP64 has no pencil variant: its pinned configuration is not a
+    candidate and the tuner's is used)"""
+    w = need_gpu()
+    force(var, block)
+    U = li.haar_links(PENCIL_L, 45)
+    psi = li.gaussian_spinor(PENCIL_L, 46, nrhs=2)
+    for prec, recon in CASES:
+        for parity, dagger in [(0, 0), (1, 1), (-1, 0), (-1, 1)]:
+            for apbc in (True, False):
+                got = run_dslash(w, PENCIL_L, U, psi, 0.13, parity, dagger, prec, recon, apbc)
+                check(prec, got, expected(PENCIL_L, U, psi, 0.13, parity, dagger, prec, recon, apbc))
+
+
+@pytest.mark.parametrize("prec,recon", [("f32", 12), ("f32", 18), ("f16", 12), ("bf16", 12)])
+def test_pencil_variants_agree_bitwise(prec, recon, monkeypatch):
+    """Pencil blocks take the time neighbours of their inner slices from LDS and
+    run the per-site arithmetic of every other variant in the same order: the
+    D-slash is the same bit for bit, for every slice count and link hint."""
+    w = need_gpu()
+    U = li.haar_links(PENCIL_L, 47)
+    psi = li.gaussian_spinor(PENCIL_L, 48, nrhs=3)
+    for parity, dagger in [(0, 0), (1, 1), (-1, 0)]:
+        ref = None
+        for c in ["0:256", "3:256", "9:128", "9:256", "9:512", "10:128", "10:256", "10:512:16"]:
+            monkeypatch.setenv("WL_TUNE_FORCE", c)
+            got = run_dslash(w, PENCIL_L, U, psi, 0.13, parity, dagger, prec, recon)
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), (prec, recon, parity, dagger, c)
+
+
+@pytest.mark.parametrize("var,block", [(9, 256), (10, 512)])
+@pytest.mark.parametrize("sloppy", ["f32", "f16"])
+def test_pencil_variant_solves(var, block, sloppy, force):
+    """A mixed-precision CGNR with every sloppy hop on pencil blocks, 3
+    right-hand sides (one block per vector; converged vectors drop out)."""
+    w = need_gpu()
+    force(var, block)
+    L = (8, 8, 8, 8)
+    U = li.near_identity_links(L, 0.3, 1008)
+    eta = li.gaussian_spinor(L, 2008, nrhs=3)
+    g = w.Gauge(L, to_dev(U))
+    x = to_dev(np.zeros_like(eta))
+    st, info = w.wilson_cg(g, to_dev(eta), x, 3, 0.1245, 1e-10, 2000, sloppy, 12, 0.1, check=False)
+    psi = from_dev(x, eta.shape)
+    g.close()
+    for r in range(3):
+        tr = np.linalg.norm(eta[r] - oracle.wilson(L, U, psi[r], 0.1245)) / np.linalg.norm(eta[r])
+        assert st == w.WL_OK and tr <= 1e-10, (var, block, sloppy, r, st, info[r], tr)
+
+
+@pytest.mark.parametrize("second", [(8, 8, 4, 8), (6, 6, 4, 10)])
+def test_pencil_variant_two_systems(second, force):
+    """A set of two systems: with 8x8x4x8 beside 8^4 the pinned pencil blocks
+    run on both; with 6x6x4x10 (72 sites per slice) pencils cannot tile the
+    second lattice, the pinned configuration is no candidate, and the tuner's
+    runs instead."""
+    w = need_gpu()
+    force(9, 256)
+    L1, L2 = (8, 8, 8, 8), second
+    U1 = li.near_identity_links(L1, 0.3, 1009)
+    U2 = li.near_identity_links(L2, 0.3, 1010)
+    e1 = li.gaussian_spinor(L1, 2009, nrhs=2)
+    e2 = li.gaussian_spinor(L2, 2010, nrhs=1)
+    g1, g2 = w.Gauge(L1, to_dev(U1)), w.Gauge(L2, to_dev(U2))
+    x1, x2 = to_dev(np.zeros_like(e1)), to_dev(np.zeros_like(e2))
+    st, info = w.wilson_cg_multi([g1, g2], [to_dev(e1), to_dev(e2)], [x1, x2], [2, 1], [0.1245, 0.124], 1e-10,
+                                 2000, "f16", 12, 0.1)
+    p1, p2 = from_dev(x1, e1.shape), from_dev(x2, e2.shape)
+    g1.close()
+    g2.close()
+    assert st == w.WL_OK, (st, info)
+    for L, U, e, p, kappa in ((L1, U1, e1, p1, 0.1245), (L2, U2, e2, p2, 0.124)):
+        for r in range(e.shape[0]):
+            tr = np.linalg.norm(e[r] - oracle.wilson(L, U, p[r], kappa)) / np.linalg.norm(e[r])
+            assert tr <= 1e-10, (second, L, r, tr)
