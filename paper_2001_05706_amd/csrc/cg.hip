@@ -452,6 +452,17 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
         // a recurrence that crawls far beyond its usual interval has lost its way
         std::vector<int> since(nv, 0), interval(nv, 8), crawl(nv, 0);
         std::vector<double> rsloppy(nv, 0.0);  // sloppy |r| at the end of the last chunk
+        // CGNR: the fastest convergence (decades of the FP64 residual per
+        // iteration) of an interval between two updates, the first interval
+        // (the start-up transient) excluded, and the count of consecutive
+        // chunks whose recurrence converged at under a third of it.  After an
+        // update that continues the search direction, a half-precision
+        // recurrence can lose conjugacy and crawl (32^3x64 FP16, delta 0.03:
+        // 0.009 decades per iteration against 0.14 before, for 144 iterations
+        // until the interval rule fired); two such chunks in a row count as a
+        // crawl, which restarts the direction.
+        std::vector<double> ref_rate(nv, 0.0);
+        std::vector<int> slow(nv, 0);
         // raise the sloppy precision one step; p is converted (restarted vectors overwrite it)
         // `folded` marks the vectors whose sloppy solution is already in the FP64
         // accumulator with a fresh FP64 residual; the others are folded in here first
@@ -534,12 +545,15 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                     rmin[v] = std::min(rmin[v], rlow);
                     if (rfirst > 0 && rlast > 0 && k > 1) {
                         // fastest convergence among the vectors sets the pace
-                        rate = std::max(rate, std::log10(rfirst / rlast) / (k - 1));
+                        const double cr = std::log10(rfirst / rlast) / (k - 1);
+                        rate = std::max(rate, cr);
                         nrate = 1;
+                        if (cg.method == M_CGNR && ref_rate[v] > 0.0)
+                            slow[v] = cr < ref_rate[v] / 3 ? slow[v] + 1 : 0;
                     }
                 }
                 since[v] += k;
-                crawl[v] = !upd[v] && since[v] > std::max(3 * interval[v], 24);
+                crawl[v] = !upd[v] && (since[v] > std::max(3 * interval[v], 24) || (slow[v] >= 2 && since[v] >= 8));
                 if (crawl[v]) upd[v] = 1;
                 if (iters[v] >= maxiter) upd[v] = 1;
                 anyupd = anyupd || upd[v];
@@ -608,6 +622,9 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                         if (stall[v] >= 2) stalled = true;
                     }
                     if (!crawl[v] && since[v] > 0) interval[v] = since[v];
+                    if (updates[v] >= 2 && since[v] > 0 && r > 0.0 && r < last_true[v])
+                        ref_rate[v] = std::max(ref_rate[v], std::log10(last_true[v] / r) / since[v]);
+                    slow[v] = 0;
                     since[v] = 0;
                     last_true[v] = r;
                     rmax[v] = rmin[v] = r;
@@ -624,6 +641,7 @@ wl_status run_cg(ExecSet &S, const double *const *eta, double *const *x, int rec
                             upd[v] = restart[v] = 1;
                             stall[v] = 0;
                             since[v] = 0;
+                            slow[v] = 0;
                         }
                 }
                 std::vector<int> cont(nv, 0), rst(nv, 0);
