@@ -106,7 +106,9 @@ __global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
         load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, q);
 #pragma unroll
         for (int k = 0; k < 24; ++k) r[k] -= al * q[k];
-        store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+        // r is the neighbour input of the next hop (of M^+): a plain store
+        // leaves it in the last-level cache also when the fields are streamed
+        store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
         nrm = site_norm2(r);
     }
     if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
@@ -130,7 +132,8 @@ __global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
         p[k] = s[k] + be * p[k];
     }
     store_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
-    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    // p is the neighbour input of the next hop (of M): plain store, as r above
+    store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
 template <int P, bool ONE = false>
