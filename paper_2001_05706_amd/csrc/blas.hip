@@ -259,7 +259,8 @@ __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
     cmul_site(br, bi, t, p);  // beta (p - omega v)
 #pragma unroll
     for (int k = 0; k < 24; ++k) p[k] += r[k];
-    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    // p is the neighbour input of the next hop: plain store (see k_r_update)
+    store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
 template <int P, bool ONE = false, bool NT = false>
@@ -276,7 +277,8 @@ __global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
     cmul_site((T)ar, (T)ai, v, av);
 #pragma unroll
     for (int k = 0; k < 24; ++k) r[k] -= av[k];
-    store_spinor<P, NT>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+    // s is the neighbour input of the next hop: plain store (see k_r_update)
+    store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
 }
 
 template <int P, bool ONE = false, bool NT = false>
