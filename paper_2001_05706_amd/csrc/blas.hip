@@ -19,6 +19,14 @@ __device__ __forceinline__ void blas_issued(int a, int b, int c, int d, int e)
     asm volatile("" ::"s"(a), "s"(b), "s"(c), "s"(d), "s"(e));
 }
 
+// Streaming hint for the store of the field the next hop reads as its
+// neighbour input (p or r in CGNR, p or s in BiCGStab): plain in FP32 and FP64,
+// so that the field waits for the hop in the last-level cache (32^3x64 FP32
+// CGNR 3% faster); with half-precision fields the plain store
+// slowed the hops as much as it sped up the updates, and the hops' share of
+// the traffic is what the links' place in that cache is kept for.
+template <int P, bool NT> constexpr bool kNextHopNT = NT && (P == P_F16 || P == P_BF16);
+
 // The block's vector vi, its descriptors and its logical block.  Every kernel
 // has the template flag ONE: instantiated true for a set of one vector, whose
 // descriptors sit at index 0, so that their loads and the block map's go out
@@ -106,9 +114,8 @@ __global__ __launch_bounds__(256) void k_r_update(BlasArgs a)
         load_spinor<P, NT>(vbase<P>(a.f[1], vd), nbase(a.fn[1], vd), sd.stride, cb, q);
 #pragma unroll
         for (int k = 0; k < 24; ++k) r[k] -= al * q[k];
-        // r is the neighbour input of the next hop (of M^+): a plain store
-        // leaves it in the last-level cache also when the fields are streamed
-        store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+        // r is the neighbour input of the next hop (of M^+)
+        store_spinor<P, kNextHopNT<P, NT>>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
         nrm = site_norm2(r);
     }
     if (a.red.kind != RED_NONE) block_reduce_store(a.red, vd.pslot0, bm.lblk, nrm);
@@ -132,8 +139,8 @@ __global__ __launch_bounds__(256) void k_xpay_x(BlasArgs a)
         p[k] = s[k] + be * p[k];
     }
     store_spinor<P, NT>(vbase<P>(a.f[2], vd), nbase(a.fn[2], vd), sd.stride, cb, x);
-    // p is the neighbour input of the next hop (of M): plain store, as r above
-    store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    // p is the neighbour input of the next hop (of M)
+    store_spinor<P, kNextHopNT<P, NT>>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
 template <int P, bool ONE = false>
@@ -259,8 +266,8 @@ __global__ __launch_bounds__(256) void k_bicg_p(BlasArgs a)
     cmul_site(br, bi, t, p);  // beta (p - omega v)
 #pragma unroll
     for (int k = 0; k < 24; ++k) p[k] += r[k];
-    // p is the neighbour input of the next hop: plain store (see k_r_update)
-    store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
+    // p is the neighbour input of the next hop
+    store_spinor<P, kNextHopNT<P, NT>>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, p);
 }
 
 template <int P, bool ONE = false, bool NT = false>
@@ -277,8 +284,8 @@ __global__ __launch_bounds__(256) void k_bicg_s(BlasArgs a)
     cmul_site((T)ar, (T)ai, v, av);
 #pragma unroll
     for (int k = 0; k < 24; ++k) r[k] -= av[k];
-    // s is the neighbour input of the next hop: plain store (see k_r_update)
-    store_spinor<P, false>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
+    // s is the neighbour input of the next hop
+    store_spinor<P, kNextHopNT<P, NT>>(vbase<P>(a.f[0], vd), nbase(a.fn[0], vd), sd.stride, cb, r);
 }
 
 template <int P, bool ONE = false, bool NT = false>

@@ -134,8 +134,8 @@ public:
     // last-level cache: eight of them (about what a solver iteration touches
     // besides the links) exceed it.  The iteration kernels then read and write
     // fields non-temporally, which keeps the links in that cache for the hops
-    // (the update kernels store the field the next hop reads -- p, r or s --
-    // plainly).
+    // (in FP32 and FP64 the update kernels store the field the next hop
+    // reads -- p, r or s -- plainly).
     // WL_STREAM_FIELDS=0 or 1 overrides the choice (tests of both forms).
     bool stream_fields(int prec) const
     {
