@@ -310,8 +310,10 @@ const char *wl_last_error(void);
  * conversion inside the timed region): `reps` back-to-back launches on
  * `stream`, measured with HIP events on that stream.  nsets >= 1 independent
  * (links, in, out) sets are rotated so that consecutive launches do not find
- * their operands in the caches (cold protocol) -- nsets = 1 is the warm
- * protocol of a solver.  Returns the mean seconds per launch. */
+ * their operands in the caches (cold protocol; its launch configuration is
+ * tuned on rotated launches too) -- nsets = 1 is the warm protocol of a
+ * solver, with the solver's tuned configuration.  Returns the mean seconds
+ * per launch. */
 wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs, int32_t parity,
                           int32_t nsets, int32_t reps, double *seconds_per_call, void *stream);
 

@@ -1325,41 +1325,53 @@ wl_status wl_bench_dslash(wl_gauge U, wl_prec prec, int32_t recon, int32_t nrhs,
     }
     const double *coef = nullptr;
     if (st == WL_OK) st = coef_table(*S, {0, 0, 0, 0, 1.0}, &coef);
-    int B = 256, cfg = cfg_make(0, 256, 4);
+    // one launch of configuration c on operand set k
+    auto launch_cfg = [&](int k, int c, const Layout *Lc) {
+        HopArgs a{};
+        a.sys = dsys[k];
+        a.vec = Lc->d_vec;
+        a.map = Lc->d_map;
+        a.active = nullptr;
+        a.nblocks = Lc->nblocks;
+        a.parity = parity;
+        a.nvec = S->nvec;
+        a.in = fin[k].p;
+        a.in_norm = fin[k].n;
+        a.out = fout[k].p;
+        a.out_norm = fout[k].n;
+        a.epi.coef = coef;
+        a.red = no_red();
+        a.one = S->nvec == 1;  // as the solvers launch it
+        a.stream = S->stream_fields(prec);
+        return launch_hop(prec, recon, false, false, cfg_var(c), a, cfg_block(c), s);
+    };
+    int cfg = cfg_make(0, 256, 4);
     const Layout *L = nullptr;
     if (st == WL_OK) {
         // tune on set 0 with the same launch the timed loop makes
         Epi e;
         e.coef = coef;
         st = hop(*S, prec, recon, false, parity, fout[0], fin[0], e, no_red(), s, false);
-        cfg = tuned_block(hop_key(*S, prec, recon, false) + "/x0", hop_cands(*S, prec, false), s,
-                          [](int) { return hipSuccess; });
-        B = cfg_block(cfg);
+        const std::string key = hop_key(*S, prec, recon, false) + "/x0";
+        const std::vector<int> cands = hop_cands(*S, prec, false);
+        cfg = tuned_block(key, cands, s, [](int) { return hipSuccess; });
+        if (st == WL_OK && nsets > 1) {
+            // cold protocol: the configuration is tuned on launches that rotate
+            // through the operand sets, as the timed loop's do
+            int rot = 0;
+            cfg = tuned_block(key + "/cold" + std::to_string(nsets), cands, s, [&](int c) -> hipError_t {
+                const Layout *Lc = nullptr;
+                if (hop_layout(*S, c, &Lc) != WL_OK) return hipErrorOutOfMemory;
+                return launch_cfg(rot++ % nsets, c, Lc);
+            });
+        }
         if (st == WL_OK) st = hop_layout(*S, cfg, &L);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == WL_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         st = set_error(WL_ERR_HIP, "event creation failed");
     if (st == WL_OK) {
-        auto launch = [&](int k) {
-            HopArgs a{};
-            a.sys = dsys[k];
-            a.vec = L->d_vec;
-            a.map = L->d_map;
-            a.active = nullptr;
-            a.nblocks = L->nblocks;
-            a.parity = parity;
-            a.nvec = S->nvec;
-            a.in = fin[k].p;
-            a.in_norm = fin[k].n;
-            a.out = fout[k].p;
-            a.out_norm = fout[k].n;
-            a.epi.coef = coef;
-            a.red = no_red();
-            a.one = S->nvec == 1;  // as the solvers launch it
-            a.stream = S->stream_fields(prec);
-            return launch_hop(prec, recon, false, false, cfg_var(cfg), a, B, s);
-        };
+        auto launch = [&](int k) { return launch_cfg(k, cfg, L); };
         for (int k = 0; k < nsets && st == WL_OK; ++k)
             if (launch(k) != hipSuccess) st = set_error(WL_ERR_HIP, "hop launch failed");
         if (st == WL_OK && hipEventRecord(e0, s) != hipSuccess) st = set_error(WL_ERR_HIP, "event record failed");
